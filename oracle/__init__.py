@@ -1,0 +1,212 @@
+"""CPU oracle for exact affine-gap local alignment -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  It shares no code with the GPU library
+(``paper_1304_5966_amd``); the only common dependency is the seeded sequence
+generator ``paper_1304_5966_amd.synth``, which holds no alignment arithmetic.
+
+``gotoh.c`` holds the dynamic programs (see its header for the exact
+recurrences, following the SW# paper, Section 2); this module loads it with
+ctypes and adds CIGAR rescoring.  ``brute.py`` holds the pure-Python
+enumerations that pin the C code.
+
+Pins (tests/test_oracle_*.py): brute-force enumeration of every local
+alignment of tiny inputs (score, endpoint, start point), a midline-filtered
+enumeration of optimal global alignments (canonical CIGAR), closed forms
+(self-alignment, a single substitution or gap in otherwise equal aperiodic
+strings), textbook reductions (linear gaps, gapless Kadane maxima) and
+invariants (swap, joint reversal, complement, alphabet permutation,
+extension monotonicity), plus the planted-alignment lower bound at scale.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gotoh.c")
+_LIB = os.path.join(_HERE, "_liboracle.so")
+
+SCORING = (1, 3, 5, 2)  # match, mismatch penalty, gap open, gap extend (all configs)
+
+
+class _Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+def build(force: bool = False) -> str:
+    """Compile gotoh.c into _liboracle.so with the host C compiler."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        u8p = ctypes.c_char_p
+        sp = ctypes.POINTER(_Scoring)
+        for name in ("orc_sw_full", "orc_sw_linear"):
+            f = getattr(L, name)
+            f.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, i64p, i64p, i64p]
+            f.restype = ctypes.c_int
+        L.orc_sw_matrix.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_void_p]
+        L.orc_sw_row_best.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_sw_start.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int64, i64p, i64p]
+        L.orc_mm_align.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64, i64p]
+        L.orc_global_score.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp,
+                                       ctypes.c_int64, ctypes.c_int64, i64p]
+        _lib = L
+    return _lib
+
+
+def _bytes(x) -> bytes:
+    if isinstance(x, bytes):
+        return x
+    if isinstance(x, str):
+        return x.encode()
+    return np.ascontiguousarray(x, dtype=np.uint8).tobytes()
+
+
+def _sc(scoring) -> _Scoring:
+    return _Scoring(*[int(v) for v in scoring])
+
+
+def sw_score(a, b, scoring=SCORING, full: bool = False):
+    """(S, end_a, end_b); end = lexicographically smallest cell holding S, 0-based; -1 if S = 0."""
+    a, b = _bytes(a), _bytes(b)
+    s, ea, eb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    f = lib().orc_sw_full if full else lib().orc_sw_linear
+    rc = f(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), ctypes.byref(s), ctypes.byref(ea),
+           ctypes.byref(eb))
+    if rc:
+        raise ValueError("oracle: invalid arguments")
+    return int(s.value), int(ea.value), int(eb.value)
+
+
+def sw_matrix(a, b, scoring=SCORING) -> np.ndarray:
+    a, b = _bytes(a), _bytes(b)
+    H = np.zeros((len(a) + 1, len(b) + 1), dtype=np.int64)
+    if lib().orc_sw_matrix(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), H.ctypes.data):
+        raise ValueError("oracle: invalid arguments")
+    return H
+
+
+def sw_row_best(a, b, scoring=SCORING):
+    a, b = _bytes(a), _bytes(b)
+    rb = np.zeros(len(a), dtype=np.int64)
+    rc = np.zeros(len(a), dtype=np.int64)
+    if lib().orc_sw_row_best(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), rb.ctypes.data,
+                             rc.ctypes.data):
+        raise ValueError("oracle: invalid arguments")
+    return rb, rc
+
+
+def sw_start(a, b, score, end_a, end_b, scoring=SCORING):
+    a, b = _bytes(a), _bytes(b)
+    sa, sb = ctypes.c_int64(), ctypes.c_int64()
+    if lib().orc_sw_start(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), score, end_a, end_b,
+                          ctypes.byref(sa), ctypes.byref(sb)):
+        raise ValueError("oracle: start not found / invalid arguments")
+    return int(sa.value), int(sb.value)
+
+
+def mm_align(a, b, scoring=SCORING, tb: int = -1, te: int = -1) -> str:
+    """Canonical Myers-Miller CIGAR of the global alignment of a x b (tb/te default: g)."""
+    a, b = _bytes(a), _bytes(b)
+    cap = 4 * (len(a) + len(b)) + 64
+    buf = ctypes.create_string_buffer(cap)
+    n = ctypes.c_int64()
+    rc = lib().orc_mm_align(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), tb, te, buf, cap,
+                            ctypes.byref(n))
+    if rc:
+        raise ValueError("oracle: mm_align failed")
+    return buf.value.decode()
+
+
+def global_score(a, b, scoring=SCORING, tb: int = -1, te: int = -1) -> int:
+    a, b = _bytes(a), _bytes(b)
+    g = scoring[2] - scoring[3]
+    out = ctypes.c_int64()
+    if lib().orc_global_score(a, len(a), b, len(b), ctypes.byref(_sc(scoring)),
+                              g if tb < 0 else tb, g if te < 0 else te, ctypes.byref(out)):
+        raise ValueError("oracle: invalid arguments")
+    return int(out.value)
+
+
+@dataclass
+class Alignment:
+    score: int
+    start_a: int
+    start_b: int
+    end_a: int
+    end_b: int
+    cigar: str
+
+
+def sw_align(a, b, scoring=SCORING) -> Alignment:
+    """Score, endpoint, start point and canonical CIGAR (empty alignment when S = 0)."""
+    a, b = _bytes(a), _bytes(b)
+    s, ea, eb = sw_score(a, b, scoring)
+    if s <= 0:
+        return Alignment(0, -1, -1, -1, -1, "")
+    sa, sb = sw_start(a, b, s, ea, eb, scoring)
+    cig = mm_align(a[sa:ea + 1], b[sb:eb + 1], scoring)
+    return Alignment(s, sa, sb, ea, eb, cig)
+
+
+_CIG = re.compile(r"(\d+)([=XID])")
+
+
+def parse_cigar(cigar: str):
+    ops = _CIG.findall(cigar)
+    if "".join(n + o for n, o in ops) != cigar:
+        raise ValueError(f"malformed CIGAR {cigar!r}")
+    return [(int(n), o) for n, o in ops]
+
+
+def rescore(a, b, start_a, start_b, cigar: str, scoring=SCORING):
+    """Score of a CIGAR placed at (start_a, start_b); checks '='/'X' against the letters.
+
+    Returns (score, end_a, end_b).  Each maximal I or D run costs open + extend*(k-1).
+    """
+    a, b = _bytes(a).upper(), _bytes(b).upper()
+    match, mismatch, go, ge = scoring
+    i, j, s = start_a, start_b, 0
+    prev = None
+    for n, o in parse_cigar(cigar):
+        if o in "=X":
+            for _ in range(n):
+                eq = a[i] == b[j]
+                if eq != (o == "="):
+                    raise ValueError(f"CIGAR op {o} disagrees with letters at ({i},{j})")
+                s += match if eq else -mismatch
+                i += 1
+                j += 1
+        else:
+            if o == prev:
+                raise ValueError("adjacent runs of the same gap op")
+            s -= go + ge * (n - 1)
+            if o == "I":
+                j += n
+            else:
+                i += n
+        prev = o
+    return s, i - 1, j - 1

@@ -1,0 +1,383 @@
+/*
+ * CPU oracle for exact local alignment with affine gaps (Smith-Waterman with
+ * Gotoh's three-state recurrence) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this file.  It shares nothing with the GPU library: no headers, no
+ * tables, no helpers.  It is written to be read against the paper, not to be
+ * fast: plain loops, 64-bit integers (so the "minus infinity" sentinel can be
+ * decremented freely), one cell at a time.
+ *
+ * What it computes (SW# paper, Section 2, and the affine-gap model stated in
+ * its abstract):
+ *   gap of length k costs   open + (k-1)*extend           (both positive)
+ *   s(x,y) = +match if x == y (case-insensitive) else -mismatch
+ *   E(i,j) = max(E(i,j-1) - extend, H(i,j-1) - open)     horizontal, consumes B  -> CIGAR 'I'
+ *   F(i,j) = max(F(i-1,j) - extend, H(i-1,j) - open)     vertical,   consumes A  -> CIGAR 'D'
+ *   H(i,j) = max(0, H(i-1,j-1) + s(A_i,B_j), E(i,j), F(i,j))
+ *   H(0,.) = H(.,0) = 0,  E(.,0) = F(0,.) = -inf
+ *
+ *  - score + endpoint (Section 2, first phase): S = max H; the endpoint is the
+ *    lexicographically smallest (i,j) -- A index first -- with H(i,j) = S.
+ *  - start point (Section 2, second phase): the same recurrence without the
+ *    zero and with minus-infinity borders except the anchor, run on the reversed
+ *    prefixes that end at the endpoint; the start is the lexicographically
+ *    smallest reversed cell whose value equals S.
+ *  - alignment (Section 2, reconstruction phase): Myers-Miller divide and
+ *    conquer on the start..end rectangle with gap cost g + h*k, g = open -
+ *    extend, h = extend; midline ties go to the smallest column, a plain
+ *    crossing before a gap-spanning one; base cases as documented at mm_rec().
+ *
+ * Every function returns 0 on success, -1 on invalid arguments.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NEG (-((int64_t)1 << 40))
+
+typedef struct {
+    int32_t match;      /* > 0 */
+    int32_t mismatch;   /* >= 0, subtracted on a mismatch */
+    int32_t gap_open;   /* cost of the first gap position */
+    int32_t gap_extend; /* cost of each further gap position */
+} orc_scoring;
+
+static int up(uint8_t c) { return (c >= 'a' && c <= 'z') ? c - 32 : c; }
+
+static int64_t sub_score(uint8_t x, uint8_t y, const orc_scoring* sc) {
+    return up(x) == up(y) ? (int64_t)sc->match : -(int64_t)sc->mismatch;
+}
+
+static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
+
+static int bad_args(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc) {
+    if (m < 0 || n < 0 || !sc) return 1;
+    if ((m > 0 && !a) || (n > 0 && !b)) return 1;
+    if (sc->match <= 0 || sc->mismatch < 0 || sc->gap_extend <= 0 || sc->gap_open < sc->gap_extend) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ full matrix */
+
+/* Full (M+1)x(N+1) matrices of H, E and F; for small inputs only. */
+int orc_sw_full(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                int64_t* score, int64_t* end_a, int64_t* end_b) {
+    if (bad_args(a, m, b, n, sc)) return -1;
+    int64_t W = n + 1;
+    int64_t* H = (int64_t*)calloc((size_t)((m + 1) * W), sizeof(int64_t));
+    int64_t* E = (int64_t*)calloc((size_t)((m + 1) * W), sizeof(int64_t));
+    int64_t* F = (int64_t*)calloc((size_t)((m + 1) * W), sizeof(int64_t));
+    if (!H || !E || !F) { free(H); free(E); free(F); return -1; }
+    for (int64_t j = 0; j <= n; j++) { H[j] = 0; E[j] = ORC_NEG; F[j] = ORC_NEG; }
+    for (int64_t i = 1; i <= m; i++) {
+        H[i * W] = 0; E[i * W] = ORC_NEG; F[i * W] = ORC_NEG;
+        for (int64_t j = 1; j <= n; j++) {
+            int64_t e = max2(E[i * W + j - 1] - sc->gap_extend, H[i * W + j - 1] - sc->gap_open);
+            int64_t f = max2(F[(i - 1) * W + j] - sc->gap_extend, H[(i - 1) * W + j] - sc->gap_open);
+            int64_t h = H[(i - 1) * W + j - 1] + sub_score(a[i - 1], b[j - 1], sc);
+            h = max2(max2(h, 0), max2(e, f));
+            E[i * W + j] = e; F[i * W + j] = f; H[i * W + j] = h;
+        }
+    }
+    int64_t best = 0, bi = -1, bj = -1;
+    for (int64_t i = 1; i <= m; i++)
+        for (int64_t j = 1; j <= n; j++)
+            if (H[i * W + j] > best) { best = H[i * W + j]; bi = i - 1; bj = j - 1; }
+    *score = best; *end_a = bi; *end_b = bj;
+    free(H); free(E); free(F);
+    return 0;
+}
+
+/* Value of every cell, for property tests on small inputs (H only, row-major (M+1)x(N+1)). */
+int orc_sw_matrix(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                  int64_t* H_out) {
+    if (bad_args(a, m, b, n, sc) || !H_out) return -1;
+    int64_t W = n + 1;
+    int64_t* E = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    int64_t* F = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    if (!E || !F) { free(E); free(F); return -1; }
+    for (int64_t j = 0; j <= n; j++) { H_out[j] = 0; F[j] = ORC_NEG; }
+    for (int64_t i = 1; i <= m; i++) {
+        int64_t e = ORC_NEG;
+        H_out[i * W] = 0;
+        for (int64_t j = 1; j <= n; j++) {
+            e = max2(e - sc->gap_extend, H_out[i * W + j - 1] - sc->gap_open);
+            F[j] = max2(F[j] - sc->gap_extend, H_out[(i - 1) * W + j] - sc->gap_open);
+            int64_t h = H_out[(i - 1) * W + j - 1] + sub_score(a[i - 1], b[j - 1], sc);
+            H_out[i * W + j] = max2(max2(h, 0), max2(e, F[j]));
+        }
+    }
+    free(E); free(F);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ linear space */
+
+/* Row by row: one row of H, one of F, one scalar E; first strict maximum in row-major order. */
+int orc_sw_linear(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                  int64_t* score, int64_t* end_a, int64_t* end_b) {
+    if (bad_args(a, m, b, n, sc)) return -1;
+    int64_t* H = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int64_t* F = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    if (!H || !F) { free(H); free(F); return -1; }
+    for (int64_t j = 0; j <= n; j++) { H[j] = 0; F[j] = ORC_NEG; }
+    int64_t best = 0, bi = -1, bj = -1;
+    for (int64_t i = 1; i <= m; i++) {
+        int64_t diag = H[0];  /* H(i-1, 0) */
+        int64_t e = ORC_NEG;
+        H[0] = 0;
+        for (int64_t j = 1; j <= n; j++) {
+            e = max2(e - sc->gap_extend, H[j - 1] - sc->gap_open);          /* H[j-1] = H(i, j-1) */
+            F[j] = max2(F[j] - sc->gap_extend, H[j] - sc->gap_open);        /* H[j]   = H(i-1, j) */
+            int64_t h = max2(max2(diag + sub_score(a[i - 1], b[j - 1], sc), 0), max2(e, F[j]));
+            diag = H[j];
+            H[j] = h;
+            if (h > best) { best = h; bi = i - 1; bj = j - 1; }
+        }
+    }
+    *score = best; *end_a = bi; *end_b = bj;
+    free(H); free(F);
+    return 0;
+}
+
+/* Best local score of every row of the matrix (property tests: pruning bounds, sampling). */
+int orc_sw_row_best(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                    int64_t* row_best, int64_t* row_col) {
+    if (bad_args(a, m, b, n, sc)) return -1;
+    int64_t* H = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int64_t* F = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    if (!H || !F) { free(H); free(F); return -1; }
+    for (int64_t j = 0; j <= n; j++) { H[j] = 0; F[j] = ORC_NEG; }
+    for (int64_t i = 1; i <= m; i++) {
+        int64_t diag = H[0], e = ORC_NEG, rb = 0, rc = -1;
+        H[0] = 0;
+        for (int64_t j = 1; j <= n; j++) {
+            e = max2(e - sc->gap_extend, H[j - 1] - sc->gap_open);
+            F[j] = max2(F[j] - sc->gap_extend, H[j] - sc->gap_open);
+            int64_t h = max2(max2(diag + sub_score(a[i - 1], b[j - 1], sc), 0), max2(e, F[j]));
+            diag = H[j];
+            H[j] = h;
+            if (h > rb) { rb = h; rc = j - 1; }
+        }
+        row_best[i - 1] = rb; row_col[i - 1] = rc;
+    }
+    free(H); free(F);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ start point */
+
+/*
+ * Anchored reverse pass: R over A^r = reverse(A[0..end_a]) and B^r = reverse(B[0..end_b]),
+ *   R_H(0,0) = 0, every other border value -inf, no zero floor;
+ * start = lexicographically smallest reversed cell (i,j) with R_H(i,j) = S,
+ * reported as (end_a - i + 1, end_b - j + 1).
+ */
+int orc_sw_start(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                 int64_t score, int64_t end_a, int64_t end_b, int64_t* start_a, int64_t* start_b) {
+    if (bad_args(a, m, b, n, sc)) return -1;
+    if (score <= 0) { *start_a = -1; *start_b = -1; return 0; }
+    if (end_a < 0 || end_a >= m || end_b < 0 || end_b >= n) return -1;
+    int64_t rm = end_a + 1, rn = end_b + 1;
+    int64_t* H = (int64_t*)malloc((size_t)(rn + 1) * sizeof(int64_t));
+    int64_t* F = (int64_t*)malloc((size_t)(rn + 1) * sizeof(int64_t));
+    if (!H || !F) { free(H); free(F); return -1; }
+    H[0] = 0;
+    for (int64_t j = 1; j <= rn; j++) H[j] = ORC_NEG;
+    for (int64_t j = 0; j <= rn; j++) F[j] = ORC_NEG;
+    int found = 0;
+    for (int64_t i = 1; i <= rm && !found; i++) {
+        int64_t diag = H[0], e = ORC_NEG;
+        H[0] = ORC_NEG;
+        uint8_t ai = a[end_a - (i - 1)];
+        for (int64_t j = 1; j <= rn; j++) {
+            e = max2(e - sc->gap_extend, H[j - 1] - sc->gap_open);
+            F[j] = max2(F[j] - sc->gap_extend, H[j] - sc->gap_open);
+            int64_t h = max2(diag + sub_score(ai, b[end_b - (j - 1)], sc), max2(e, F[j]));
+            diag = H[j];
+            H[j] = h;
+            if (h == score) {
+                *start_a = end_a - i + 1; *start_b = end_b - j + 1;
+                found = 1;
+                break;
+            }
+        }
+    }
+    free(H); free(F);
+    return found ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------ Myers-Miller */
+
+typedef struct {
+    char* ops;
+    int64_t* lens;
+    int64_t n, cap;
+    int failed;
+} orc_cigar;
+
+static void cig_push(orc_cigar* c, char op, int64_t k) {
+    if (k <= 0 || c->failed) return;
+    if (c->n > 0 && c->ops[c->n - 1] == op) { c->lens[c->n - 1] += k; return; }
+    if (c->n == c->cap) {
+        int64_t nc = c->cap ? 2 * c->cap : 64;
+        char* o = (char*)realloc(c->ops, (size_t)nc);
+        int64_t* l = (int64_t*)realloc(c->lens, (size_t)nc * sizeof(int64_t));
+        if (!o || !l) { c->failed = 1; if (o) c->ops = o; if (l) c->lens = l; return; }
+        c->ops = o; c->lens = l; c->cap = nc;
+    }
+    c->ops[c->n] = op; c->lens[c->n] = k; c->n++;
+}
+
+typedef struct {
+    const orc_scoring* sc;
+    int64_t g, h;                 /* gap of length k costs g + h*k */
+    int64_t *CC, *DD, *RR, *SS;   /* scratch rows, length >= N+1 */
+    uint8_t *ra, *rb;             /* scratch for reversed copies */
+} mm_ctx;
+
+static int64_t gapc(const mm_ctx* x, int64_t k) { return k > 0 ? x->g + x->h * k : 0; }
+
+/*
+ * Forward half: C(i,j) best path (0,0)->(i,j), D(i,j) best such path whose last
+ * edge is vertical (a deletion of A_i).  A vertical run leaving (0,0) opens at
+ * cost tb instead of g.  Writes C(M,.) to CC and D(M,.) to DD.
+ */
+static void mm_forward(const mm_ctx* x, const uint8_t* A, int64_t M, const uint8_t* B, int64_t N,
+                       int64_t tb, int64_t* CC, int64_t* DD) {
+    CC[0] = 0;
+    DD[0] = ORC_NEG;
+    for (int64_t j = 1; j <= N; j++) { CC[j] = -gapc(x, j); DD[j] = ORC_NEG; }
+    for (int64_t i = 1; i <= M; i++) {
+        int64_t diag = CC[0];
+        CC[0] = -(tb + x->h * i);
+        DD[0] = CC[0];
+        int64_t ins = ORC_NEG;
+        for (int64_t j = 1; j <= N; j++) {
+            ins = max2(ins - x->h, CC[j - 1] - x->g - x->h);
+            DD[j] = max2(DD[j] - x->h, CC[j] - x->g - x->h);
+            int64_t c = max2(diag + sub_score(A[i - 1], B[j - 1], x->sc), max2(DD[j], ins));
+            diag = CC[j];
+            CC[j] = c;
+        }
+    }
+}
+
+static void mm_rec(mm_ctx* x, const uint8_t* A, int64_t M, const uint8_t* B, int64_t N,
+                   int64_t tb, int64_t te, orc_cigar* out) {
+    if (N == 0) { cig_push(out, 'D', M); return; }
+    if (M == 0) { cig_push(out, 'I', N); return; }
+    if (M == 1) {
+        /* (i) delete A_0 and insert all of B as one run; the deletion sits next
+         *     to the cheaper open side (first unless te < tb);
+         * (ii) align A_0 with B_k (smallest k among the best), insert the rest. */
+        int64_t open_i = tb < te ? tb : te;
+        int64_t v_i = -(open_i + x->h) - gapc(x, N);
+        int64_t v_ii = ORC_NEG, k_ii = -1;
+        for (int64_t k = 1; k <= N; k++) {
+            int64_t v = -gapc(x, k - 1) + sub_score(A[0], B[k - 1], x->sc) - gapc(x, N - k);
+            if (v > v_ii) { v_ii = v; k_ii = k; }
+        }
+        if (v_ii >= v_i) {
+            cig_push(out, 'I', k_ii - 1);
+            cig_push(out, up(A[0]) == up(B[k_ii - 1]) ? '=' : 'X', 1);
+            cig_push(out, 'I', N - k_ii);
+        } else if (te < tb) {
+            cig_push(out, 'I', N);
+            cig_push(out, 'D', 1);
+        } else {
+            cig_push(out, 'D', 1);
+            cig_push(out, 'I', N);
+        }
+        return;
+    }
+    int64_t mid = M / 2;
+    /* forward over A[0..mid), reverse over A[mid..M) */
+    mm_forward(x, A, mid, B, N, tb, x->CC, x->DD);
+    int64_t rm = M - mid;
+    for (int64_t i = 0; i < rm; i++) x->ra[i] = A[M - 1 - i];
+    for (int64_t j = 0; j < N; j++) x->rb[j] = B[N - 1 - j];
+    mm_forward(x, x->ra, rm, x->rb, N, te, x->RR, x->SS);
+    /* RR/SS are indexed by reversed column: suffix starting at column j is index N-j */
+    int64_t best = ORC_NEG, bj = -1;
+    int type = 0;
+    for (int64_t j = 0; j <= N; j++) {
+        int64_t v1 = x->CC[j] + x->RR[N - j];
+        if (v1 > best) { best = v1; bj = j; type = 1; }
+        int64_t v2 = x->DD[j] + x->SS[N - j] + x->g;
+        if (v2 > best) { best = v2; bj = j; type = 2; }
+    }
+    if (type == 1) {
+        mm_rec(x, A, mid, B, bj, tb, x->g, out);
+        mm_rec(x, A + mid, M - mid, B + bj, N - bj, x->g, te, out);
+    } else {
+        mm_rec(x, A, mid - 1, B, bj, tb, 0, out);
+        cig_push(out, 'D', 2);
+        mm_rec(x, A + mid + 1, M - mid - 1, B + bj, N - bj, 0, te, out);
+    }
+}
+
+/* Writes the run-length CIGAR of the canonical alignment of A[0..M) x B[0..N) into buf. */
+int orc_mm_align(const uint8_t* A, int64_t M, const uint8_t* B, int64_t N, const orc_scoring* sc,
+                 int64_t tb, int64_t te, char* buf, int64_t cap, int64_t* out_len) {
+    if (bad_args(A, M, B, N, sc) || !buf || cap <= 0) return -1;
+    mm_ctx x;
+    x.sc = sc;
+    x.g = (int64_t)sc->gap_open - sc->gap_extend;
+    x.h = sc->gap_extend;
+    int64_t W = N + 1;
+    x.CC = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    x.DD = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    x.RR = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    x.SS = (int64_t*)malloc((size_t)W * sizeof(int64_t));
+    x.ra = (uint8_t*)malloc((size_t)(M + 1));
+    x.rb = (uint8_t*)malloc((size_t)(N + 1));
+    orc_cigar c = {0};
+    int rc = -1;
+    if (x.CC && x.DD && x.RR && x.SS && x.ra && x.rb) {
+        if (tb < 0) tb = x.g;
+        if (te < 0) te = x.g;
+        mm_rec(&x, A, M, B, N, tb, te, &c);
+        if (!c.failed) {
+            int64_t pos = 0;
+            rc = 0;
+            for (int64_t k = 0; k < c.n; k++) {
+                char tmp[32];
+                int64_t v = c.lens[k];
+                int t = 0;
+                do { tmp[t++] = (char)('0' + v % 10); v /= 10; } while (v);
+                if (pos + t + 1 >= cap) { rc = -2; break; }
+                while (t) buf[pos++] = tmp[--t];
+                buf[pos++] = c.ops[k];
+            }
+            buf[pos < cap ? pos : cap - 1] = 0;
+            *out_len = pos;
+        }
+    }
+    free(x.CC); free(x.DD); free(x.RR); free(x.SS); free(x.ra); free(x.rb);
+    free(c.ops); free(c.lens);
+    return rc;
+}
+
+/* Best global score of A x B with the tb/te convention above (for tests). */
+int orc_global_score(const uint8_t* A, int64_t M, const uint8_t* B, int64_t N, const orc_scoring* sc,
+                     int64_t tb, int64_t te, int64_t* out) {
+    if (bad_args(A, M, B, N, sc)) return -1;
+    mm_ctx x;
+    x.sc = sc;
+    x.g = (int64_t)sc->gap_open - sc->gap_extend;
+    x.h = sc->gap_extend;
+    if (N == 0) { *out = M ? -((tb < te ? tb : te) + x.h * M) : 0; return 0; }
+    int64_t* CC = (int64_t*)malloc((size_t)(N + 1) * sizeof(int64_t));
+    int64_t* DD = (int64_t*)malloc((size_t)(N + 1) * sizeof(int64_t));
+    if (!CC || !DD) { free(CC); free(DD); return -1; }
+    (void)te;
+    mm_forward(&x, A, M, B, N, tb, CC, DD);
+    /* a trailing deletion run ending at (M,N) opens at te instead of g */
+    int64_t v = CC[N];
+    if (M > 0) v = max2(v, DD[N] + x.g - te);
+    *out = v;
+    free(CC); free(DD);
+    return 0;
+}

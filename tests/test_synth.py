@@ -1,0 +1,68 @@
+"""The seeded generators: reproducible, rates as specified, transcripts consistent."""
+import numpy as np
+
+from paper_1304_5966_amd import synth
+
+
+def _apply(src, out, tr):
+    """Replay a transcript: every '=' base equals its source, every 'X' differs."""
+    i = j = 0
+    for o, n in zip(tr.ops.tolist(), tr.lens.tolist()):
+        o = chr(o)
+        if o == "=":
+            assert np.array_equal(src[i:i + n], out[j:j + n])
+            i += n
+            j += n
+        elif o == "X":
+            assert np.all(src[i:i + n] != out[j:j + n])
+            i += n
+            j += n
+        elif o == "I":
+            j += n
+        else:
+            i += n
+    return i, j
+
+
+def test_reproducible():
+    a = synth.config1()
+    b = synth.config1()
+    assert np.array_equal(a.a, b.a) and np.array_equal(a.b, b.b)
+    assert a.a.size == 10_000 and a.b.size == 8_000
+    p = synth.config3_pair(17)
+    q = synth.config3_pair(17)
+    assert np.array_equal(p.a, q.a) and np.array_equal(p.b, q.b)
+    assert set(np.unique(p.a).tobytes()) <= set(b"ACGT")
+
+
+def test_mutation_rates_and_transcript():
+    rng = synth.rng_for(5)
+    src = synth.random_dna(rng, 200_000)
+    out, tr = synth.mutate(rng, src, 0.05, 0.005)
+    i, j = _apply(src, out, tr)
+    assert i == src.size and j == out.size
+    ops = {chr(o): int(n) for o, n in zip(*np.unique(np.repeat(tr.ops, 1), return_counts=True))}
+    n_sub = int(tr.lens[tr.ops == ord("X")].sum())
+    # binomial 5 % of 200k: sd ~ 97; allow 6 sd
+    assert abs(n_sub - 10_000 * (1 - 0.005 * 1.5)) < 700
+    n_events = int((tr.ops == ord("I")).sum() + (tr.ops == ord("D")).sum())
+    assert 800 < n_events < 1200
+    mean_len = tr.lens[(tr.ops == ord("I")) | (tr.ops == ord("D"))].mean()
+    assert 2.5 < mean_len < 3.6
+    assert ops
+
+
+def test_planted_transcripts_replay():
+    for p in (synth.config1(), synth.config3_pair(0), synth.config3_pair(2)):
+        pl = p.planted[0]
+        i, j = _apply(p.a[pl.a_off:], p.b[pl.b_off:], pl.transcript)
+        assert i == pl.a_len
+        assert pl.b_off + j <= p.b.size
+
+
+def test_config3_shape():
+    lens = np.array([[synth.config3_pair(i).a.size, synth.config3_pair(i).b.size]
+                     for i in range(0, 400)])
+    assert lens.min() >= 100 and lens.max() <= 20_000
+    # log-uniform: median near sqrt(100 * 20000) ~ 1414
+    assert 900 < np.median(lens) < 2200
