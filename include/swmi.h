@@ -1,0 +1,157 @@
+/*
+ * swmi -- exact affine-gap Smith-Waterman on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libswmi.so.  Every entry point returns an sw_status; none aborts.
+ * On failure a thread-local message is available from sw_last_error().
+ *
+ * The computation follows SW# (Korpar & Sikic, arXiv 1304.5966), Section 2:
+ *   first phase  -- forward local-alignment pass over the whole matrix in
+ *                   linear memory, giving the best score and its endpoint;
+ *   second phase -- reverse pass from the endpoint with minus-infinity
+ *                   borders and no zero floor, giving the start point;
+ *   reconstruction -- Myers-Miller divide and conquer between start and end,
+ *                   giving the alignment.
+ * Affine gaps as in the paper's abstract: a gap of length k costs
+ *   gap_open + (k - 1) * gap_extend.
+ *
+ * Conventions shared by every call:
+ *  - Sequences are DNA letters "ACGTacgt" (case-insensitive).  Any other byte
+ *    makes the call fail with SW_EINVAL and names the offset.
+ *  - A indexes rows (the reference), B indexes columns.
+ *  - Coordinates are 0-based and inclusive.  When the best score is 0 the
+ *    alignment is empty: start = end = -1 and the CIGAR is "".
+ *  - Ties: the endpoint is the lexicographically smallest (end_a, end_b)
+ *    holding the best score; the start is the lexicographically largest
+ *    (start_a, start_b) from which that endpoint is reached with the best
+ *    score; the alignment is the canonical Myers-Miller path (midline ties go
+ *    to the smallest column, a plain crossing before a gap-spanning one).
+ *  - CIGAR: run-length "=" (equal pair), "X" (unequal pair), "I" (consumes B
+ *    only), "D" (consumes A only).
+ *  - Host input buffers are borrowed read-only for the duration of the call;
+ *    result structs are caller-owned (sw_align_result's CIGAR is freed with
+ *    sw_align_result_free).
+ *  - Device pointers, where taken, must be valid on the context's device and
+ *    ordered on the context's stream; the call synchronizes that stream
+ *    before returning results to host memory.
+ */
+#ifndef SWMI_H
+#define SWMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_EINVAL = -1,        /* bad argument: null pointer, bad letter, bad scoring */
+    SW_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
+    SW_EDEVICE = -3,       /* a HIP runtime call or kernel failed */
+    SW_EUNSUPPORTED = -4,  /* arguments valid but outside what the kernels handle */
+    SW_EINTERNAL = -5      /* internal consistency check failed */
+} sw_status;
+
+/* Scoring (all configurations of the benchmark: 1, 3, 5, 2).
+ * Requirements: 0 < match <= 127, 0 <= mismatch <= 127,
+ * 0 < gap_extend <= gap_open, gap_open <= 2^20.  Otherwise SW_EINVAL.
+ * If match * min(len_a, len_b) >= 2^30 the call returns SW_EUNSUPPORTED
+ * (int32 headroom). */
+typedef struct {
+    int32_t match;       /* added for equal letters */
+    int32_t mismatch;    /* subtracted for unequal letters */
+    int32_t gap_open;    /* cost of a gap of length 1 */
+    int32_t gap_extend;  /* cost of each further gap position */
+} sw_scoring;
+
+typedef enum {
+    SW_PRUNE_NONE = 0,     /* every cell is computed */
+    SW_PRUNE_BEST = 1,     /* skip tiles that cannot reach the running best (exact; paper Section 2, pruning) */
+    SW_PRUNE_LEARNED = 2   /* as BEST, plus a threshold T predicted by the model; exact, with a rerun on a miss */
+} sw_prune_mode;
+
+typedef struct sw_model sw_model;
+
+typedef struct {
+    int32_t prune_mode;        /* sw_prune_mode */
+    int32_t threshold;         /* > 0: use this T instead of the model's prediction (LEARNED mode) */
+    const sw_model* model;     /* LEARNED mode: threshold model (sw_model_load) */
+    int32_t rows_per_lane;     /* 0 = autotuned; else 4, 8 or 16 */
+    int32_t waves_per_cu;      /* 0 = autotuned; else 1..16 resident stripe waves per CU */
+    int32_t band_width;        /* 0 = automatic; else columns per band, a positive multiple of 64 */
+    int32_t flags;             /* reserved, 0 */
+} sw_options;
+
+typedef struct {
+    int32_t score;             /* best local score S >= 0 */
+    int32_t threshold;         /* pruning threshold T that was used (0 if none) */
+    int64_t end_a;             /* endpoint row (A index), -1 if S == 0 */
+    int64_t end_b;             /* endpoint column (B index), -1 if S == 0 */
+    int64_t cells_computed;    /* DP cells evaluated by the score pass (pruned tiles excluded) */
+    int32_t fallback;          /* 1 if T exceeded the found maximum and the plain pass was rerun */
+    int32_t reserved;
+} sw_score_result;
+
+typedef struct {
+    int32_t score;
+    int32_t reserved;
+    int64_t start_a, start_b;  /* first aligned pair, -1 if score == 0 */
+    int64_t end_a, end_b;      /* last aligned pair, -1 if score == 0 */
+    char* cigar;               /* NUL-terminated, owned by the library: sw_align_result_free */
+    int64_t cigar_len;
+} sw_align_result;
+
+typedef struct sw_context sw_context;
+
+/* Last error message of the calling thread ("" if none).  Valid until the next call. */
+const char* sw_last_error(void);
+
+/* Library version string. */
+const char* sw_version(void);
+
+/* Creates a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  A context caches device
+ * workspace and tuning; it is not thread-safe: use one per stream. */
+sw_status sw_context_create(int device, void* hip_stream, sw_context** out);
+sw_status sw_context_destroy(sw_context* ctx);
+
+/* First phase (paper Section 2): best local score and its endpoint.
+ * a[0..len_a), b[0..len_b): host letters.  out: caller-owned. */
+sw_status sw_score(sw_context* ctx, const char* a, int64_t len_a, const char* b, int64_t len_b,
+                   const sw_scoring* scoring, const sw_options* options, sw_score_result* out);
+
+/* Same as sw_score on device-resident letters (d_a, d_b on the context's
+ * device).  The workspace (device, at least sw_score_workspace_size bytes,
+ * owned by the caller) holds every intermediate; nothing else is allocated. */
+size_t sw_score_workspace_size(sw_context* ctx, int64_t len_a, int64_t len_b, const sw_options* options);
+sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const uint8_t* d_b,
+                       int64_t len_b, const sw_scoring* scoring, const sw_options* options,
+                       void* d_workspace, size_t workspace_bytes, sw_score_result* out);
+
+/* All three phases (paper Section 2): score, start, end and the canonical
+ * CIGAR.  out->cigar is allocated by the library; release it with
+ * sw_align_result_free. */
+sw_status sw_align(sw_context* ctx, const char* a, int64_t len_a, const char* b, int64_t len_b,
+                   const sw_scoring* scoring, const sw_options* options, sw_align_result* out);
+void sw_align_result_free(sw_align_result* r);
+
+/* Second phase alone (paper Section 2): the start point of the best alignment
+ * that ends at (end_a, end_b) with score `score` (as returned by sw_score). */
+sw_status sw_start(sw_context* ctx, const char* a, int64_t len_a, const char* b, int64_t len_b,
+                   const sw_scoring* scoring, int32_t score, int64_t end_a, int64_t end_b,
+                   int64_t* start_a, int64_t* start_b);
+
+/* Many independent pairs in one persistent launch.  Pair p is
+ * seqs_a[offs_a[p] .. offs_a[p+1]) against seqs_b[offs_b[p] .. offs_b[p+1])
+ * (host letters, offs_* of length n_pairs + 1, non-decreasing).
+ * out[0 .. n_pairs) receives score and endpoint per pair. */
+sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t* offs_a, const char* seqs_b,
+                   const int64_t* offs_b, int32_t n_pairs, const sw_scoring* scoring,
+                   const sw_options* options, sw_score_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWMI_H */

@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libswmi.so (declared in include/swmi.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch is used for device memory (workspaces and
+device-resident sequences) and for the current HIP stream.  If the library has
+not been built, importing this module raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libswmi.so")
+
+SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EUNSUPPORTED, SW_EINTERNAL = 0, -1, -2, -3, -4, -5
+PRUNE_NONE, PRUNE_BEST, PRUNE_LEARNED = 0, 1, 2
+DEFAULT_SCORING = (1, 3, 5, 2)
+
+
+class SwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"swmi status {status}: {msg}")
+        self.status = status
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("prune_mode", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("model", ctypes.c_void_p), ("rows_per_lane", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("band_width", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class ScoreResult(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("end_a", ctypes.c_int64), ("end_b", ctypes.c_int64),
+                ("cells_computed", ctypes.c_int64), ("fallback", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class AlignResult(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("start_a", ctypes.c_int64), ("start_b", ctypes.c_int64),
+                ("end_a", ctypes.c_int64), ("end_b", ctypes.c_int64),
+                ("cigar", ctypes.c_void_p), ("cigar_len", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1304_5966_amd.build`")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.sw_last_error.restype = ctypes.c_char_p
+    L.sw_version.restype = ctypes.c_char_p
+    L.sw_context_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.sw_context_destroy.argtypes = [vp]
+    L.sw_score.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring),
+                           ctypes.POINTER(Options), ctypes.POINTER(ScoreResult)]
+    L.sw_score_workspace_size.argtypes = [vp, i64, i64, ctypes.POINTER(Options)]
+    L.sw_score_workspace_size.restype = ctypes.c_size_t
+    L.sw_score_dev.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(Scoring), ctypes.POINTER(Options),
+                               vp, ctypes.c_size_t, ctypes.POINTER(ScoreResult)]
+    L.sw_align.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring),
+                           ctypes.POINTER(Options), ctypes.POINTER(AlignResult)]
+    L.sw_align_result_free.argtypes = [ctypes.POINTER(AlignResult)]
+    L.sw_align_result_free.restype = None
+    L.sw_start.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring), i32,
+                           i64, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sw_batch.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.c_char_p,
+                           ctypes.POINTER(i64), i32, ctypes.POINTER(Scoring), ctypes.POINTER(Options),
+                           ctypes.POINTER(ScoreResult)]
+    for name in ("sw_context_create", "sw_context_destroy", "sw_score", "sw_score_dev", "sw_align",
+                 "sw_start", "sw_batch"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy", "sw_score",
+            "sw_score_workspace_size", "sw_score_dev", "sw_align", "sw_align_result_free", "sw_start",
+            "sw_batch")
+
+
+def _check(status: int):
+    if status != SW_OK:
+        raise SwError(status, lib.sw_last_error().decode(errors="replace"))
+
+
+def _bytes(x) -> bytes:
+    if isinstance(x, bytes):
+        return x
+    if isinstance(x, str):
+        return x.encode()
+    return np.ascontiguousarray(x, dtype=np.uint8).tobytes()
+
+
+def _options(prune=PRUNE_NONE, threshold=0, rows_per_lane=0, waves_per_cu=0, band_width=0,
+             model=None) -> Options:
+    return Options(int(prune), int(threshold), model, int(rows_per_lane), int(waves_per_cu),
+                   int(band_width), 0)
+
+
+@dataclass
+class Score:
+    score: int
+    end_a: int
+    end_b: int
+    cells_computed: int = 0
+    threshold: int = 0
+    fallback: int = 0
+
+    def key(self):
+        return (self.score, self.end_a, self.end_b)
+
+
+@dataclass
+class Alignment:
+    score: int
+    start_a: int
+    start_b: int
+    end_a: int
+    end_b: int
+    cigar: str
+
+
+def _score_of(r: ScoreResult) -> Score:
+    return Score(r.score, r.end_a, r.end_b, r.cells_computed, r.threshold, r.fallback)
+
+
+class Context:
+    """A library context on one device, bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.sw_context_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            lib.sw_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host-pointer entry points
+    def score(self, a, b, scoring=DEFAULT_SCORING, **opts) -> Score:
+        a, b = _bytes(a), _bytes(b)
+        r = ScoreResult()
+        _check(lib.sw_score(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+                            ctypes.byref(_options(**opts)), ctypes.byref(r)))
+        return _score_of(r)
+
+    def align(self, a, b, scoring=DEFAULT_SCORING, **opts) -> Alignment:
+        a, b = _bytes(a), _bytes(b)
+        r = AlignResult()
+        _check(lib.sw_align(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+                            ctypes.byref(_options(**opts)), ctypes.byref(r)))
+        try:
+            cig = ctypes.string_at(r.cigar, r.cigar_len).decode() if r.cigar else ""
+            return Alignment(r.score, r.start_a, r.start_b, r.end_a, r.end_b, cig)
+        finally:
+            lib.sw_align_result_free(ctypes.byref(r))
+
+    def start(self, a, b, score, end_a, end_b, scoring=DEFAULT_SCORING):
+        a, b = _bytes(a), _bytes(b)
+        sa, sb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.sw_start(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+                            int(score), int(end_a), int(end_b), ctypes.byref(sa), ctypes.byref(sb)))
+        return sa.value, sb.value
+
+    def batch(self, pairs, scoring=DEFAULT_SCORING, **opts):
+        a_parts = [_bytes(p[0]) for p in pairs]
+        b_parts = [_bytes(p[1]) for p in pairs]
+        offs_a = np.zeros(len(pairs) + 1, dtype=np.int64)
+        offs_b = np.zeros(len(pairs) + 1, dtype=np.int64)
+        offs_a[1:] = np.cumsum([len(x) for x in a_parts])
+        offs_b[1:] = np.cumsum([len(x) for x in b_parts])
+        return self.batch_packed(b"".join(a_parts), offs_a, b"".join(b_parts), offs_b, scoring, **opts)
+
+    def batch_packed(self, seqs_a, offs_a, seqs_b, offs_b, scoring=DEFAULT_SCORING, **opts):
+        offs_a = np.ascontiguousarray(offs_a, dtype=np.int64)
+        offs_b = np.ascontiguousarray(offs_b, dtype=np.int64)
+        n = len(offs_a) - 1
+        out = (ScoreResult * max(n, 1))()
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(lib.sw_batch(self.handle, _bytes(seqs_a), offs_a.ctypes.data_as(i64p), _bytes(seqs_b),
+                            offs_b.ctypes.data_as(i64p), n, ctypes.byref(Scoring(*scoring)),
+                            ctypes.byref(_options(**opts)), out))
+        return [_score_of(out[i]) for i in range(n)]
+
+    # -- device-pointer entry point (torch-owned buffers, no allocation in the library)
+    def workspace_size(self, len_a: int, len_b: int, **opts) -> int:
+        return int(lib.sw_score_workspace_size(self.handle, len_a, len_b, ctypes.byref(_options(**opts))))
+
+    def workspace(self, nbytes: int):
+        torch = self._torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def score_dev(self, d_a, d_b, scoring=DEFAULT_SCORING, workspace=None, **opts) -> Score:
+        """d_a, d_b: uint8 CUDA tensors of letters on this context's device."""
+        la, lb = int(d_a.numel()), int(d_b.numel())
+        need = self.workspace_size(la, lb, **opts)
+        ws = workspace if workspace is not None else self.workspace(need)
+        r = ScoreResult()
+        _check(lib.sw_score_dev(self.handle, ctypes.c_void_p(d_a.data_ptr()), la,
+                                ctypes.c_void_p(d_b.data_ptr()), lb, ctypes.byref(Scoring(*scoring)),
+                                ctypes.byref(_options(**opts)), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel(), ctypes.byref(r)))
+        return _score_of(r)
+
+
+def version() -> str:
+    return lib.sw_version().decode()
