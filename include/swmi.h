@@ -150,6 +150,28 @@ sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t* offs_a, c
                    const int64_t* offs_b, int32_t n_pairs, const sw_scoring* scoring,
                    const sw_options* options, sw_score_result* out);
 
+/* The reconstruction's host part (paper Section 2: small sub-matrices are
+ * aligned on the CPU): canonical Myers-Miller alignment of the whole of
+ * a x b (host letters) as a global alignment whose leading / trailing deletion
+ * runs open at tb / te (-1 = gap_open - gap_extend; 0 = continuing a run), gap
+ * cost g + h*k otherwise.  If score_known, `score` must be the optimal global
+ * score; it restricts the work to the diagonals that score can reach.  Writes
+ * a NUL-terminated CIGAR of at most cap bytes.  Host only, no device use. */
+sw_status sw_mm_host(const char* a, int64_t len_a, const char* b, int64_t len_b, const sw_scoring* scoring,
+                     int32_t tb, int32_t te, int32_t score_known, int64_t score, char* cigar, int64_t cap,
+                     int64_t* cigar_len);
+
+/* sw_batch on device-resident letters: d_seqs_a / d_seqs_b hold the packed
+ * letters on the context's device, indexed by the host offset arrays offs_a /
+ * offs_b exactly as in sw_batch.  The device workspace (caller-owned, at least
+ * sw_batch_workspace_size bytes) holds every intermediate. */
+size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b, int32_t n_pairs,
+                               const sw_scoring* scoring, const sw_options* options);
+sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* offs_a, const uint8_t* d_seqs_b,
+                       const int64_t* offs_b, int32_t n_pairs, const sw_scoring* scoring,
+                       const sw_options* options, void* d_workspace, size_t workspace_bytes,
+                       sw_score_result* out);
+
 #ifdef __cplusplus
 }
 #endif

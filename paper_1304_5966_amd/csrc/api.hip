@@ -1,15 +1,17 @@
-// Host side of libswmi: argument checks, workspace planning, launches, C ABI.
+// Host side of libswmi: errors, context, argument checks, engine planning and
+// launch, and the score entry points of the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 
 #include "swmi.h"
-#include "swmi_internal.h"
 #include "swmi_host.h"
+#include "swmi_internal.h"
 
 using namespace swmi;
 
@@ -27,14 +29,16 @@ sw_status swmi::fail(sw_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
         if (e_ != hipSuccess) return fail(SW_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 extern "C" const char* sw_last_error(void) { return g_err.c_str(); }
-extern "C" const char* sw_version(void) { return "swmi 0.1 (gfx950)"; }
+extern "C" const char* sw_version(void) { return "swmi 0.2 (gfx950)"; }
+
+size_t swmi::align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ------------------------------------------------------------------------ context
 
@@ -48,13 +52,15 @@ extern "C" sw_status sw_context_create(int device, void* hip_stream, sw_context*
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(SW_EUNSUPPORTED, "sw_context_create: device is %s, kernels are built for gfx950", prop.gcnArchName);
+        return fail(SW_EUNSUPPORTED, "sw_context_create: device is %s, kernels are built for gfx950",
+                    prop.gcnArchName);
     sw_context* c = new (std::nothrow) sw_context();
     if (!c) return fail(SW_ENOMEM, "sw_context_create: out of host memory");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->num_cu = prop.multiProcessorCount;
-    hipError_t e = hipHostMalloc((void**)&c->host_misc, 4096, hipHostMallocDefault);
+    c->host_misc_bytes = (size_t)64 << 10;
+    hipError_t e = hipHostMalloc((void**)&c->host_misc, c->host_misc_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return fail(SW_ENOMEM, "sw_context_create: hipHostMalloc: %s", hipGetErrorString(e));
@@ -95,6 +101,14 @@ sw_status swmi::ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out) 
     return SW_OK;
 }
 
+sw_status swmi::read_back(sw_context* ctx, const void* dev, size_t bytes, void** host) {
+    if (bytes > ctx->host_misc_bytes) return fail(SW_EINTERNAL, "read_back of %zu bytes", bytes);
+    HIP_TRY(hipMemcpyAsync(ctx->host_misc, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *host = ctx->host_misc;
+    return SW_OK;
+}
+
 // ------------------------------------------------------------------------ checks
 
 sw_status swmi::check_scoring(const sw_scoring* s) {
@@ -103,7 +117,8 @@ sw_status swmi::check_scoring(const sw_scoring* s) {
     if (s->mismatch < 0 || s->mismatch > 127)
         return fail(SW_EINVAL, "mismatch must be in 0..127 (got %d)", s->mismatch);
     if (s->gap_extend <= 0 || s->gap_open < s->gap_extend || s->gap_open > (1 << 20))
-        return fail(SW_EINVAL, "need 0 < gap_extend <= gap_open <= 2^20 (got %d, %d)", s->gap_open, s->gap_extend);
+        return fail(SW_EINVAL, "need 0 < gap_extend <= gap_open <= 2^20 (got %d, %d)", s->gap_open,
+                    s->gap_extend);
     return SW_OK;
 }
 
@@ -130,117 +145,191 @@ sw_status swmi::check_options(const sw_options* o) {
     return SW_OK;
 }
 
-// ------------------------------------------------------------------------ plan
+// ------------------------------------------------------------------------ engine plan
 
-static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-ScorePlan swmi::plan_score(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o) {
-    ScorePlan p{};
-    p.R = (o && o->rows_per_lane) ? o->rows_per_lane : 8;
-    const int wpc = (o && o->waves_per_cu) ? o->waves_per_cu : 8;
-    p.M = M;
-    p.N = N;
-    p.Q = (M + kWave * p.R - 1) / (kWave * p.R);
-    // Band width: keep the stripe slots within a fixed budget.
+EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>& specs, bool local,
+                             int rows_per_lane, int waves_per_cu, int band_width) {
+    EnginePlan p;
+    p.local = local;
+    p.R = rows_per_lane ? rows_per_lane : 8;
+    const int wpc = waves_per_cu ? waves_per_cu : 8;
+    const int64_t rows_per_stripe = (int64_t)kWave * p.R;
+    // Largest-first order keeps the long problems from trailing the launch.
+    std::vector<size_t> order(specs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return (double)specs[x].M * (double)specs[x].N > (double)specs[y].M * (double)specs[y].N;
+    });
     const int64_t max_grid = (int64_t)ctx->num_cu * wpc;
+    int64_t stripes = 0, maxN = 64;
+    for (const auto& s : specs) {
+        stripes += (s.M + rows_per_stripe - 1) / rows_per_stripe;
+        maxN = std::max(maxN, s.N);
+    }
+    // Band width: keep the slots (one per resident wave) within a fixed budget.
+    const int64_t grid_est = std::max<int64_t>(1, std::min<int64_t>(max_grid, stripes * ((maxN + 63) / 64)));
     const size_t slot_budget = (size_t)8 << 30;
-    int64_t grid_est = std::max<int64_t>(1, std::min<int64_t>(max_grid, p.Q * ((N + 63) / 64)));
-    int64_t nslot = grid_est + 1;
-    int64_t W = (int64_t)(slot_budget / ((size_t)nslot * sizeof(int2))) - (kSlotPad + 2 * kTick);
-    W = std::max<int64_t>(kTick, W / kTick * kTick);
-    if (o && o->band_width) W = o->band_width;
-    const int64_t N64 = (N + kTick - 1) / kTick * kTick;
-    p.W = std::min(W, std::max<int64_t>(kTick, N64));
-    p.n_bands = (N + p.W - 1) / p.W;
-    const int64_t n_tasks = p.Q * p.n_bands;
-    p.grid = (int)std::min<int64_t>(max_grid, n_tasks);
+    int64_t Wg = (int64_t)(slot_budget / ((size_t)(grid_est + 1) * sizeof(int2))) - (kSlotPad + 2 * kTick);
+    Wg = std::max<int64_t>(kTick, Wg / kTick * kTick);
+    if (band_width) Wg = band_width;
+
+    int64_t task = 0, lrow = 0, Wmax = kTick;
+    p.probs.reserve(specs.size());
+    p.order.assign(order.begin(), order.end());
+    for (size_t oi : order) {
+        const ProbSpec& s = specs[oi];
+        Prob pr{};
+        pr.a_off = s.a_off;
+        pr.b_off = s.b_off;
+        pr.M = s.M;
+        pr.N = s.N;
+        const int64_t N64 = (s.N + kTick - 1) / kTick * kTick;
+        pr.W = std::min(Wg, std::max<int64_t>(kTick, N64));
+        pr.n_bands = (s.N + pr.W - 1) / pr.W;
+        pr.Q = (s.M + rows_per_stripe - 1) / rows_per_stripe;
+        pr.task0 = task;
+        pr.lbuf_off = lrow;
+        pr.out_off = s.out_off;
+        pr.d_lo = s.d_lo;
+        pr.d_hi = s.d_hi;
+        pr.top_kind = s.top_kind;
+        pr.left_kind = s.left_kind;
+        pr.top_open = s.top_open;
+        pr.left_open = s.left_open;
+        pr.target = s.target;
+        pr.prune = s.prune;
+        pr.track = s.track;
+        task += pr.Q * pr.n_bands;
+        if (pr.n_bands > 1) lrow += pr.Q * rows_per_stripe;
+        Wmax = std::max(Wmax, pr.W);
+        p.probs.push_back(pr);
+    }
+    p.n_probs = (int64_t)p.probs.size();
+    p.n_tasks = task;
+    p.lbuf_rows = lrow;
+    p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, task));
     p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1);
-    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + p.W + 2 * kTick), 64);
+    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
 
     size_t off = 0;
-    p.off_a = off;
-    off = align_up(off + (size_t)M + 64, 256);
-    p.off_b = off;
-    off = align_up(off + (size_t)(kBPad + N + kBPadTail), 256);
+    p.off_probs = off;
+    off = align_up(off + (size_t)p.n_probs * sizeof(Prob), 256);
     p.off_slots = off;
     off = align_up(off + (size_t)p.nslot * p.slot_stride * sizeof(int2), 256);
     p.off_lbuf = off;
-    off = align_up(off + (p.n_bands > 1 ? (size_t)M * sizeof(int2) : 0), 256);
+    off = align_up(off + (size_t)p.lbuf_rows * sizeof(int2), 256);
     p.off_recs = off;
-    off = align_up(off + (size_t)n_tasks * sizeof(TaskRec), 256);
-    p.off_zero = off;  // progress + misc: cleared on every call
+    off = align_up(off + (size_t)p.n_tasks * sizeof(TaskRec), 256);
+    p.off_outs = off;
+    off = align_up(off + (size_t)p.n_probs * sizeof(ScoreOut), 256);
+    p.off_zero = off;  // cleared on every launch
     p.off_prog = off;
-    off = align_up(off + (size_t)n_tasks * sizeof(int32_t), 256);
+    off = align_up(off + (size_t)p.n_tasks * sizeof(int32_t), 256);
+    p.off_gbest = off;
+    off = align_up(off + (size_t)p.n_probs * sizeof(int32_t), 256);
+    p.off_pruned = off;
+    off = align_up(off + (size_t)p.n_probs * sizeof(unsigned long long), 256);
     p.off_misc = off;
-    off = align_up(off + 256, 256);
+    off = align_up(off + MISC_BYTES, 256);
     p.zero_bytes = off - p.off_zero;
     p.total = off;
     return p;
 }
 
-// misc block layout (bytes)
-enum { MISC_TICKET = 0, MISC_GBEST = 4, MISC_PRUNED = 8, MISC_BAD_A = 16, MISC_BAD_B = 24, MISC_OUT = 64 };
-static const unsigned long long kBadBase = 1ull << 62;
-
-sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
-                          const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
-                          sw_score_result* out) {
-    const ScorePlan p = plan_score(ctx, M, N, o);
-    if (ws_bytes < p.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, p.total);
+sw_status swmi::run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
+                           const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f) {
     uint8_t* base = (uint8_t*)ws;
-    uint8_t* misc = base + p.off_misc;
     hipStream_t st = ctx->stream;
-    HIP_TRY(launch_zero(base + p.off_zero, p.zero_bytes, st));
-    HIP_TRY(launch_encode(d_a, M, base + p.off_a, 0, 64, (unsigned long long*)(misc + MISC_BAD_A), st));
-    HIP_TRY(launch_encode(d_b, N, base + p.off_b, kBPad, kBPadTail, (unsigned long long*)(misc + MISC_BAD_B), st));
-
-    const int prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
-    const int32_t thr = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
-    FwdArgs a{};
-    a.a = base + p.off_a;
-    a.b = base + p.off_b + kBPad;
-    a.M = M;
-    a.N = N;
+    HIP_TRY(launch_zero(base + plan.off_zero, plan.zero_bytes, st));
+    HIP_TRY(hipMemcpyAsync(base + plan.off_probs, plan.probs.data(), (size_t)plan.n_probs * sizeof(Prob),
+                           hipMemcpyHostToDevice, st));
+    EngineArgs a{};
+    a.probs = (const Prob*)(base + plan.off_probs);
+    a.n_probs = plan.n_probs;
+    a.n_tasks = plan.n_tasks;
+    a.a_codes = a_codes;
+    a.b_codes = b_codes;
     a.match = sc->match;
     a.mismatch = sc->mismatch;
     a.open = sc->gap_open;
     a.ext = sc->gap_extend;
-    a.Q = p.Q;
-    a.W = p.W;
-    a.n_bands = p.n_bands;
-    a.slots = (int2*)(base + p.off_slots);
-    a.slot_stride = p.slot_stride;
-    a.nslot = p.nslot;
-    a.progress = (int32_t*)(base + p.off_prog);
-    a.ticket = (uint32_t*)(misc + MISC_TICKET);
-    a.gbest = (int32_t*)(misc + MISC_GBEST);
-    a.lbuf = (int2*)(base + p.off_lbuf);
-    a.recs = (TaskRec*)(base + p.off_recs);
-    a.pruned_cells = (unsigned long long*)(misc + MISC_PRUNED);
-    a.prune = prune;
-    a.threshold = thr;
-    HIP_TRY(launch_fwd(a, p.R, p.grid, st));
-    HIP_TRY(launch_reduce(a.recs, p.Q * p.n_bands, N, (ScoreOut*)(misc + MISC_OUT), st));
-    HIP_TRY(hipMemcpyAsync(ctx->host_misc, misc, 128, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    a.slots = (int2*)(base + plan.off_slots);
+    a.slot_stride = plan.slot_stride;
+    a.nslot = plan.nslot;
+    a.progress = (int32_t*)(base + plan.off_prog);
+    a.ticket = (uint32_t*)(base + plan.off_misc + MISC_TICKET);
+    a.gbest = (int32_t*)(base + plan.off_gbest);
+    a.lbuf = (int2*)(base + plan.off_lbuf);
+    a.recs = (TaskRec*)(base + plan.off_recs);
+    a.pruned = (unsigned long long*)(base + plan.off_pruned);
+    a.out_h = out_h;
+    a.out_f = out_f;
+    HIP_TRY(launch_engine(a, plan.R, plan.local, plan.grid, st));
+    HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.pruned, st));
+    return SW_OK;
+}
 
-    const uint8_t* hm = (const uint8_t*)ctx->host_misc;
-    unsigned long long bad_a, bad_b, pruned;
-    std::memcpy(&bad_a, hm + MISC_BAD_A, 8);
-    std::memcpy(&bad_b, hm + MISC_BAD_B, 8);
-    std::memcpy(&pruned, hm + MISC_PRUNED, 8);
+// ------------------------------------------------------------------------ score pass
+
+static std::vector<ProbSpec> score_spec(int64_t M, int64_t N, const sw_options* o) {
+    ProbSpec s;
+    s.a_off = 0;
+    s.b_off = kBPad;
+    s.M = M;
+    s.N = N;
+    s.prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
+    s.target = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
+    s.track = 1;
+    return {s};
+}
+
+// Score workspace: [a codes][b codes with padding][encode flags][engine region]
+static size_t codes_bytes(int64_t M, int64_t N) {
+    return align_up((size_t)M + 64, 256) + align_up((size_t)(kBPad + N + kBPadTail), 256) + 256;
+}
+
+size_t swmi::score_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o) {
+    const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
+                                     o ? o->waves_per_cu : 0, o ? o->band_width : 0);
+    return codes_bytes(M, N) + p.total;
+}
+
+sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
+                          const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
+                          sw_score_result* out) {
+    const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
+                                     o ? o->waves_per_cu : 0, o ? o->band_width : 0);
+    const size_t need = codes_bytes(M, N) + p.total;
+    if (ws_bytes < need) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    uint8_t* a_codes = (uint8_t*)ws;
+    uint8_t* b_codes = a_codes + align_up((size_t)M + 64, 256);
+    uint8_t* flags = (uint8_t*)ws + codes_bytes(M, N) - 256;
+    uint8_t* eng = (uint8_t*)ws + codes_bytes(M, N);
+    hipStream_t st = ctx->stream;
+    HIP_TRY(launch_zero(flags, 256, st));
+    HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, 0, (unsigned long long*)flags, st));
+    HIP_TRY(launch_encode(d_b, N, b_codes, kBPad, kBPadTail, 0, (unsigned long long*)(flags + 8), st));
+    sw_status s = run_engine(ctx, p, a_codes, b_codes, sc, eng, nullptr, nullptr);
+    if (s != SW_OK) return s;
+    uint8_t* hm = (uint8_t*)ctx->host_misc;
+    HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hm + 64, eng + p.off_outs, sizeof(ScoreOut), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    unsigned long long bad_a, bad_b;
+    std::memcpy(&bad_a, hm, 8);
+    std::memcpy(&bad_b, hm + 8, 8);
     if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
     if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
     ScoreOut so;
-    std::memcpy(&so, hm + MISC_OUT, sizeof so);
+    std::memcpy(&so, hm + 64, sizeof so);
     if (so.status) return fail(SW_EINTERNAL, "score pass: endpoint of the best score was not tracked");
     std::memset(out, 0, sizeof *out);
     out->score = so.score;
     out->end_a = so.end_a;
     out->end_b = so.end_b;
-    out->threshold = thr;
+    out->threshold = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
     const unsigned long long total = (unsigned long long)M * (unsigned long long)N;
-    out->cells_computed = (int64_t)(pruned >= total ? 0 : total - pruned);
+    out->cells_computed = (int64_t)(so.pruned_cells >= total ? 0 : total - so.pruned_cells);
     return SW_OK;
 }
 
@@ -248,7 +337,7 @@ sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const 
 
 extern "C" size_t sw_score_workspace_size(sw_context* ctx, int64_t len_a, int64_t len_b, const sw_options* o) {
     if (!ctx || len_a < 0 || len_b < 0) return 0;
-    return plan_score(ctx, len_a, len_b, o).total;
+    return score_workspace_size(ctx, len_a, len_b, o);
 }
 
 extern "C" sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const uint8_t* d_b,
@@ -270,16 +359,16 @@ extern "C" sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t l
     return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, d_workspace, workspace_bytes, out);
 }
 
-// Validates host letters on the host (so the offset of a bad letter is exact) and uploads them.
+// Uploads host letters into the context's input buffer (checked on the device).
 sw_status swmi::upload_pair(sw_context* ctx, const char* a, int64_t la, const char* b, int64_t lb,
                             uint8_t** d_a, uint8_t** d_b) {
     void* buf;
-    sw_status st = ctx_buffer(ctx, BUF_INPUT, (size_t)la + (size_t)lb + 512, &buf);
+    sw_status st = ctx_buffer(ctx, BUF_INPUT, align_up((size_t)la + 1, 256) + (size_t)lb + 256, &buf);
     if (st != SW_OK) return st;
     *d_a = (uint8_t*)buf;
     *d_b = (uint8_t*)buf + align_up((size_t)la + 1, 256);
-    HIP_TRY(hipMemcpyAsync(*d_a, a, (size_t)la, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(*d_b, b, (size_t)lb, hipMemcpyHostToDevice, ctx->stream));
+    if (la) HIP_TRY(hipMemcpyAsync(*d_a, a, (size_t)la, hipMemcpyHostToDevice, ctx->stream));
+    if (lb) HIP_TRY(hipMemcpyAsync(*d_b, b, (size_t)lb, hipMemcpyHostToDevice, ctx->stream));
     return SW_OK;
 }
 
@@ -299,7 +388,7 @@ extern "C" sw_status sw_score(sw_context* ctx, const char* a, int64_t len_a, con
     HIP_TRY(hipSetDevice(ctx->device));
     uint8_t *d_a, *d_b;
     if ((st = upload_pair(ctx, a, len_a, b, len_b, &d_a, &d_b)) != SW_OK) return st;
-    const size_t need = plan_score(ctx, len_a, len_b, options).total;
+    const size_t need = score_workspace_size(ctx, len_a, len_b, options);
     void* ws;
     if ((st = ctx_buffer(ctx, BUF_WORK, need, &ws)) != SW_OK) return st;
     return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, ws, need, out);

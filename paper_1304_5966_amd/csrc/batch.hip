@@ -1,0 +1,190 @@
+// Many independent pairs in one persistent launch of the wavefront engine.
+//
+// Every pair is a local problem of the engine's table; problems are ordered
+// largest first and share the launch's resident waves through the ticket
+// counter (a small pair is one or a few stripe tasks, a large one many), so
+// uneven lengths balance without per-pair launches.  Results come back per
+// pair: score and endpoint under the same tie rule as sw_score.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "swmi.h"
+#include "swmi_host.h"
+#include "swmi_internal.h"
+
+using namespace swmi;
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(SW_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct BatchLayout {
+    std::vector<ProbSpec> specs;
+    std::vector<int32_t> pair_of_spec;       // spec index -> pair index
+    std::vector<int64_t> a_src, a_dst, a_len;  // encode tables
+    std::vector<int64_t> b_src, b_dst, b_len;
+    int64_t a_bytes = 0, b_bytes = 0;
+    size_t off_a = 0, off_b = 0, off_tab = 0, off_flags = 0, off_eng = 0, total = 0;
+    EnginePlan plan;
+};
+
+sw_status make_layout(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b, int32_t n,
+                      const sw_scoring* sc, const sw_options* o, BatchLayout& L) {
+    if (n < 0) return fail(SW_EINVAL, "sw_batch: n_pairs < 0");
+    if (n > 0 && (!offs_a || !offs_b)) return fail(SW_EINVAL, "sw_batch: NULL offsets");
+    int64_t bpos = 0;
+    for (int32_t p = 0; p < n; ++p) {
+        const int64_t la = offs_a[p + 1] - offs_a[p], lb = offs_b[p + 1] - offs_b[p];
+        if (la < 0 || lb < 0) return fail(SW_EINVAL, "sw_batch: offsets of pair %d decrease", p);
+        sw_status st = check_lengths(la, lb, sc);
+        if (st != SW_OK) return st;
+        L.a_src.push_back(offs_a[p]);
+        L.a_dst.push_back(offs_a[p] - offs_a[0]);
+        L.a_len.push_back(la);
+        L.b_src.push_back(offs_b[p]);
+        L.b_dst.push_back(bpos + kBPad);
+        L.b_len.push_back(lb);
+        if (la > 0 && lb > 0) {
+            ProbSpec s;
+            s.a_off = offs_a[p] - offs_a[0];
+            s.b_off = bpos + kBPad;
+            s.M = la;
+            s.N = lb;
+            s.prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
+            s.target = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
+            s.track = 1;
+            L.specs.push_back(s);
+            L.pair_of_spec.push_back(p);
+        }
+        bpos += kBPad + lb + kBPadTail;
+    }
+    L.a_bytes = n ? offs_a[n] - offs_a[0] : 0;
+    L.b_bytes = bpos;
+    L.plan = plan_engine(ctx, L.specs, true, o ? o->rows_per_lane : 0, o ? o->waves_per_cu : 0,
+                         o ? o->band_width : 0);
+    size_t off = 0;
+    L.off_a = off;
+    off = align_up(off + (size_t)L.a_bytes + 64, 256);
+    L.off_b = off;
+    off = align_up(off + (size_t)L.b_bytes + 128, 256);
+    L.off_tab = off;
+    off = align_up(off + (size_t)n * 6 * sizeof(int64_t), 256);
+    L.off_flags = off;
+    off = align_up(off + 256, 256);
+    L.off_eng = off;
+    off += L.plan.total;
+    L.total = off;
+    return SW_OK;
+}
+
+sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
+                    BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out) {
+    if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    for (int32_t p = 0; p < n; ++p) {
+        std::memset(&out[p], 0, sizeof out[p]);
+        out[p].end_a = out[p].end_b = -1;
+    }
+    if (L.specs.empty()) return SW_OK;
+    uint8_t* base = (uint8_t*)ws;
+    hipStream_t s = ctx->stream;
+    int64_t* tab = (int64_t*)(base + L.off_tab);
+    std::vector<int64_t> h_tab((size_t)n * 6);
+    std::copy(L.a_src.begin(), L.a_src.end(), h_tab.begin());
+    std::copy(L.a_dst.begin(), L.a_dst.end(), h_tab.begin() + n);
+    std::copy(L.a_len.begin(), L.a_len.end(), h_tab.begin() + 2 * (size_t)n);
+    std::copy(L.b_src.begin(), L.b_src.end(), h_tab.begin() + 3 * (size_t)n);
+    std::copy(L.b_dst.begin(), L.b_dst.end(), h_tab.begin() + 4 * (size_t)n);
+    std::copy(L.b_len.begin(), L.b_len.end(), h_tab.begin() + 5 * (size_t)n);
+    HIP_TRY(hipMemcpyAsync(tab, h_tab.data(), h_tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_zero(base + L.off_flags, 256, s));
+    HIP_TRY(launch_fill_i32((int32_t*)(base + L.off_b), 0x04040404, (size_t)(L.b_bytes + 64 + 3) / 4, s));
+    unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
+    HIP_TRY(launch_encode_many(d_a, tab, tab + n, tab + 2 * (size_t)n, n, base + L.off_a, bad, s));
+    HIP_TRY(launch_encode_many(d_b, tab + 3 * (size_t)n, tab + 4 * (size_t)n, tab + 5 * (size_t)n, n,
+                               base + L.off_b, bad + 1, s));
+    uint8_t* eng = base + L.off_eng;
+    sw_status st = run_engine(ctx, L.plan, base + L.off_a, base + L.off_b, sc, eng, nullptr, nullptr);
+    if (st != SW_OK) return st;
+    std::vector<ScoreOut> so((size_t)L.plan.n_probs);
+    unsigned long long flags[2];
+    HIP_TRY(hipMemcpyAsync(flags, bad, sizeof flags, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(so.data(), eng + L.plan.off_outs, so.size() * sizeof(ScoreOut), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0]) return fail(SW_EINVAL, "seqs_a: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[0]);
+    if (flags[1]) return fail(SW_EINVAL, "seqs_b: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[1]);
+    for (size_t k = 0; k < so.size(); ++k) {
+        const int32_t p = L.pair_of_spec[(size_t)L.plan.order[k]];
+        if (so[k].status) return fail(SW_EINTERNAL, "batch: endpoint of pair %d was not tracked", p);
+        sw_score_result& r = out[p];
+        r.score = so[k].score;
+        r.end_a = so[k].end_a;
+        r.end_b = so[k].end_b;
+        const unsigned long long cells =
+            (unsigned long long)L.specs[(size_t)L.plan.order[k]].M * (unsigned long long)L.specs[(size_t)L.plan.order[k]].N;
+        r.cells_computed = (int64_t)(so[k].pruned_cells >= cells ? 0 : cells - so[k].pruned_cells);
+        r.threshold = L.specs[(size_t)L.plan.order[k]].target;
+    }
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b,
+                                          int32_t n_pairs, const sw_scoring* scoring, const sw_options* options) {
+    if (!ctx || !scoring) return 0;
+    BatchLayout L;
+    if (make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L) != SW_OK) return 0;
+    return L.total;
+}
+
+extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* offs_a,
+                                  const uint8_t* d_seqs_b, const int64_t* offs_b, int32_t n_pairs,
+                                  const sw_scoring* scoring, const sw_options* options, void* d_workspace,
+                                  size_t workspace_bytes, sw_score_result* out) {
+    if (!ctx || (n_pairs > 0 && !out)) return fail(SW_EINVAL, "sw_batch_dev: NULL context or results");
+    sw_status st;
+    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    if ((st = check_options(options)) != SW_OK) return st;
+    BatchLayout L;
+    if ((st = make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L)) != SW_OK) return st;
+    if (n_pairs > 0 && (!d_seqs_a || !d_seqs_b)) return fail(SW_EINVAL, "sw_batch_dev: NULL sequences");
+    if (!L.specs.empty() && !d_workspace) return fail(SW_EINVAL, "sw_batch_dev: NULL workspace");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return run_batch(ctx, d_seqs_a, d_seqs_b, n_pairs, scoring, L, d_workspace, workspace_bytes, out);
+}
+
+extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t* offs_a, const char* seqs_b,
+                              const int64_t* offs_b, int32_t n_pairs, const sw_scoring* scoring,
+                              const sw_options* options, sw_score_result* out) {
+    if (!ctx || (n_pairs > 0 && !out)) return fail(SW_EINVAL, "sw_batch: NULL context or results");
+    sw_status st;
+    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    if ((st = check_options(options)) != SW_OK) return st;
+    BatchLayout L;
+    if ((st = make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L)) != SW_OK) return st;
+    if (n_pairs == 0) return SW_OK;
+    if ((L.a_bytes && !seqs_a) || (L.b_bytes && !seqs_b)) return fail(SW_EINVAL, "sw_batch: NULL sequences");
+    HIP_TRY(hipSetDevice(ctx->device));
+    // the letters are uploaded at their own offsets: device index = host offset - offs[0]
+    void* in;
+    const int64_t na = offs_a[n_pairs] - offs_a[0], nb = offs_b[n_pairs] - offs_b[0];
+    if ((st = ctx_buffer(ctx, BUF_INPUT, align_up((size_t)na + 1, 256) + (size_t)nb + 256, &in)) != SW_OK)
+        return st;
+    uint8_t* d_a = (uint8_t*)in;
+    uint8_t* d_b = d_a + align_up((size_t)na + 1, 256);
+    if (na) HIP_TRY(hipMemcpyAsync(d_a, seqs_a + offs_a[0], (size_t)na, hipMemcpyHostToDevice, ctx->stream));
+    if (nb) HIP_TRY(hipMemcpyAsync(d_b, seqs_b + offs_b[0], (size_t)nb, hipMemcpyHostToDevice, ctx->stream));
+    // make_layout uses absolute offsets for the sources; shift them to the uploaded copy
+    for (auto& v : L.a_src) v -= offs_a[0];
+    for (auto& v : L.b_src) v -= offs_b[0];
+    void* ws;
+    if ((st = ctx_buffer(ctx, BUF_WORK, L.total, &ws)) != SW_OK) return st;
+    return run_batch(ctx, d_a, d_b, n_pairs, scoring, L, ws, L.total, out);
+}

@@ -1,0 +1,660 @@
+// Wavefront engine for the affine-gap dynamic programs of SW# (paper Section 2)
+// on gfx950: the first-phase local pass, the anchored reverse pass and the
+// global (Needleman-Wunsch) halves of the Myers-Miller reconstruction.
+//
+// One launch solves a table of independent problems.  Rows are codes of A,
+// columns codes of B; DP coordinates are 1-based with borders at row/column 0.
+//
+//   local  (first phase; E/F clamped at 0, exact for H since a non-positive gap
+//           value never beats the zero floor):
+//     E = max(E' - ext, H' - open, 0)   F = max(F' - ext, H' - open)
+//     H = max(Hdiag + s, E, F)          (>= 0 through E)
+//   global (reverse pass, reconstruction): the same without the zero;
+//           "minus infinity" is kNeg = -2^30.
+//
+// Work decomposition (the paper's wavefront of cell blocks, mapped to wave64):
+//  * A stripe is 64*R consecutive rows; lane l owns rows l*R .. l*R+R-1 of it
+//    and at step t works on column t-l (anti-diagonal skew of one column per
+//    lane).  H, E and H-open live in int32 VGPRs.
+//  * Each step the lane below receives the lane above's last-row H and its
+//    F-candidate max(F - ext, H - open) through DPP wave_shr:1; lane 0
+//    receives the row above the stripe through the DPP "old" operand, read
+//    from an LDS staging ring.
+//  * Substitution scores: per row a 4-byte table s(a_row, c), c = 0..3; one
+//    v_perm_b32 with four column codes as selector yields four score bytes,
+//    consumed by sign-extended byte-select adds.
+//  * Columns are cut into bands of W; a task is (problem, band, stripe), taken
+//    from an in-order ticket counter (problems in decreasing size, then band,
+//    then stripe).  A task only waits on older tasks: the stripe above in the
+//    same band (its bottom row streamed through a global slot with a published
+//    column count), the same stripe in the previous band (its right boundary
+//    H,E per row) and the task that last read the slot being reused.  The
+//    oldest unfinished task never waits: no deadlock, no residency assumption.
+//  * Every 64 steps (a tick) the wave exchanges 64 boundary columns: the next
+//    tick's inputs are prefetched, lane 63's outputs go to the task's slot and
+//    the column count is published with release semantics.
+//  * Tile skipping (paper Section 2, pruning and banding): before a tick,
+//    UB = max(every H on the tick's input borders [, 0]) + match * min(rows
+//    left, columns left); the tick is skipped if UB is strictly below
+//    max(running best, target), or if it lies outside the kept diagonal band.
+//    A skipped tick outputs lower bounds (0 / -inf).  Exact by induction along
+//    an optimal path.  Tasks entirely outside the band do no DP at all.
+//  * First cell of the best score: each lane keeps the running maximum of each
+//    of its rows; a tick that raised a row maximum to at least max(running
+//    best, target) is replayed from a register snapshot to find the first
+//    column holding it.
+#include "swmi_internal.h"
+
+namespace swmi {
+
+// ------------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int dpp_shr1(int old, int src) {
+    // wave_shr:1, bound_ctrl off: lane l <- src of lane l-1; lane 0 keeps `old`
+    return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ int sext_byte(uint32_t w, int i) { return ((int)(w << (24 - 8 * i))) >> 24; }
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ int load_acquire(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_release(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until *flag >= need; `seen` caches the last value read with acquire semantics.
+__device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need, int32_t& seen) {
+    while (seen < need) {
+        seen = load_acquire(flag);
+        if (seen < need) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ uint32_t row_table(int code, int match, int mismatch) {
+    if (code > 3) return kPadTable;
+    const uint32_t mm = (uint32_t)(uint8_t)(int8_t)(-mismatch) * 0x01010101u;
+    const int sh = 8 * code;
+    return (mm & ~(0xffu << sh)) | ((uint32_t)(uint8_t)match << sh);
+}
+
+// H on row 0 (top) or column 0 (left) at distance k >= 1 from the corner; a
+// BORDER_GAP border is a gap run from the corner whose first position costs
+// open_cost and every further one ext.
+__device__ __forceinline__ int border_h(int kind, int open_cost, int ext, int64_t k) {
+    if (kind == BORDER_ZERO) return 0;
+    if (kind == BORDER_NEG) return kNeg;
+    return (int)(-((int64_t)open_cost + (int64_t)ext * (k - 1)));
+}
+
+template <int R>
+struct WaveState {
+    int H[R];      // H of the lane's rows at the last column processed
+    int E[R];      // E (clamped at 0 in the local recurrence)
+    int HA[R];     // H - open
+    int best[R];   // running maximum of each row
+    int pos[R];    // first column holding best[] (-1 when not tracked)
+    uint32_t T[R]; // substitution table of each row
+    int hup;       // H received from the row above at the previous step (next diagonal of the first row)
+    int hl, gl;    // this lane's last-row H and F-candidate of the previous step (DPP sources)
+};
+
+struct TickCtx {
+    const int2* in;       // LDS: 64 lane-0 inputs {H, F-candidate} of this tick
+    int2* out;            // LDS: 64 lane-63 outputs
+    int2* lbuf;           // right-boundary store for the next band (capture)
+    int32_t* out_h;       // last-row outputs (reconstruction halves)
+    int32_t* out_f;
+    int64_t row0;         // lbuf index of this lane's first row
+    int64_t col0;         // problem column of step 0 for lane 0
+    int64_t out_base;     // out index of band column 0's DP column (c0 + 1)
+    int lane;
+    int rel0;             // band-relative column of step 0 for lane 0
+    int W;                // band width
+    int M_rows;           // rows of this lane inside the matrix (0..R)
+    int open, ext;
+    int out_lane, out_k;  // lane and sub-row holding the last row (-1 if not in this stripe)
+    bool capture;         // store H,E at the band's last column into lbuf
+};
+
+// One tick: 64 steps of the skewed stripe.
+//  TRACK: replay -- no outputs, no maxima; records the first column where a
+//         wanted row reaches its maximum.
+//  SLOW:  per-step predicates -- lanes left of the band's first column hold
+//         their state (tick 0); H,E at the band's last column go to lbuf; the
+//         last matrix row's H and F go to out_h/out_f.
+template <int R, bool LOCAL, bool TRACK, bool SLOW>
+__device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, const TickCtx& c,
+                                         const bool (&want)[R]) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
+    uint32_t lo = src[0], hi = src[1];
+#pragma unroll 1
+    for (int g = 0; g < kTick / 4; ++g) {
+        const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
+        lo = hi;
+        hi = src[g + 2];
+        uint32_t sc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, s.T[k], cw);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = 4 * g + i;
+            const int2 in = c.in[m];
+            const int upH = dpp_shr1(in.x, s.hl);
+            const int upG = dpp_shr1(in.y, s.gl);
+            int diag = s.hup;
+            s.hup = upH;
+            int F = upG;
+            const int rel = c.rel0 + m - c.lane;
+            const bool act = SLOW ? (rel >= 0) : true;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int Hd = diag + sext_byte(sc[k], i);
+                const int En = LOCAL ? max(max(s.E[k] - c.ext, s.HA[k]), 0) : max(s.E[k] - c.ext, s.HA[k]);
+                const int Hn = max(max(Hd, En), F);
+                const int HAn = Hn - c.open;
+                if (SLOW) {
+                    if (!TRACK && c.out_k == k && c.lane == c.out_lane && act && rel < c.W) {
+                        c.out_h[c.out_base + rel] = Hn;
+                        c.out_f[c.out_base + rel] = F;
+                    }
+                }
+                F = max(F - c.ext, HAn);
+                diag = s.H[k];
+                if (SLOW) {
+                    if (act) {
+                        s.H[k] = Hn;
+                        s.E[k] = En;
+                        s.HA[k] = HAn;
+                    }
+                    if (!TRACK && c.capture && rel == c.W - 1 && k < c.M_rows)
+                        c.lbuf[c.row0 + k] = make_int2(Hn, En);
+                } else {
+                    s.H[k] = Hn;
+                    s.E[k] = En;
+                    s.HA[k] = HAn;
+                }
+                if (TRACK) {
+                    if (act && want[k] && s.pos[k] < 0 && Hn == s.best[k]) s.pos[k] = (int)(c.col0 + m - c.lane);
+                } else if (SLOW) {
+                    if (act) s.best[k] = max(s.best[k], Hn);
+                } else {
+                    s.best[k] = max(s.best[k], Hn);
+                }
+            }
+            s.hl = s.H[R - 1];
+            s.gl = F;
+            if (!TRACK && c.lane == kWave - 1) c.out[m] = make_int2(s.hl, s.gl);
+        }
+    }
+}
+
+// Does task (band, stripe q) of problem `pr` hold any cell of the kept diagonal band?
+__device__ __forceinline__ bool task_active(const Prob& pr, int64_t band, int64_t q, int R) {
+    if (pr.d_lo <= -kNoBand && pr.d_hi >= kNoBand) return true;
+    const int64_t R0 = q * (int64_t)(kWave * R);
+    const int64_t R1 = min(R0 + (int64_t)(kWave * R), pr.M);
+    const int64_t c0 = band * pr.W;
+    const int64_t W = min(pr.W, pr.N - c0);
+    const int64_t dmin = c0 + 1 - R1, dmax = c0 + W - R0 - 1;
+    return !(dmax < pr.d_lo || dmin > pr.d_hi);
+}
+
+template <int R, bool LOCAL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void engine_kernel(
+    EngineArgs p) {
+    __shared__ int2 in_ring[2][kTick];
+    __shared__ int2 out_buf[kTick];
+    constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
+    const int lane = threadIdx.x;
+
+    for (;;) {
+        uint32_t tk = 0;
+        if (lane == 0) tk = atomicAdd(p.ticket, 1u);
+        const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+        if (task >= p.n_tasks) break;
+        int64_t lo = 0, hi = p.n_probs - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (p.probs[mid].task0 <= task) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t pi = lo;
+        const Prob pr = p.probs[pi];
+        const int64_t t = task - pr.task0;
+        const int64_t band = t / pr.Q;
+        const int64_t q = t - band * pr.Q;
+        const int64_t c0 = band * pr.W;
+        const int W = (int)min(pr.W, pr.N - c0);
+        const int n_ticks = (W + 2 * kTick - 2) / kTick;  // ceil((W + 63) / 64)
+        const int64_t R0 = q * (int64_t)(kWave * R);
+        const int64_t R1 = min(R0 + (int64_t)(kWave * R), pr.M);
+        const int64_t row0 = R0 + (int64_t)lane * R;
+        const bool capture = band + 1 < pr.n_bands;
+        const uint8_t* acodes = p.a_codes + pr.a_off;
+        const uint8_t* bcodes = p.b_codes + pr.b_off;
+        int2* lbuf = p.lbuf + pr.lbuf_off;
+        int2* my_slot = p.slots + (task % p.nslot) * p.slot_stride;
+        const int2* prod_slot = q > 0 ? p.slots + ((task - 1) % p.nslot) * p.slot_stride : nullptr;
+        const int32_t* prod_prog = p.progress + (task - 1);
+        int32_t prod_seen = 0;
+        int32_t* gbest = p.gbest + pi;
+
+        // Older tasks this one depends on.
+        if (task >= p.nslot) {
+            int32_t seen = 0;
+            wait_at_least(p.progress + task - p.nslot + 1, kDone, seen);
+        }
+        if (band > 0) {
+            int32_t seen = 0;
+            wait_at_least(p.progress + task - pr.Q, kDone, seen);
+        }
+        const bool left_active = band > 0 && task_active(pr, band - 1, q, R);
+
+        if (!task_active(pr, band, q, R)) {
+            // Entirely outside the kept band: only the values the neighbours read.
+            if (lane == 0) {
+                int hlast = kNeg;
+                if (band == 0) hlast = border_h(pr.left_kind, pr.left_open, p.ext, R1);
+                else if (left_active) hlast = lbuf[R1 - 1].x;
+                my_slot[kSlotPad - 1] = make_int2(hlast, 0);
+                TaskRec r;
+                r.score = kNeg;
+                r.pad = 0;
+                r.row = R0;
+                r.col = -1;
+                p.recs[task] = r;
+            }
+            if (capture)
+                for (int64_t row = R0 + lane; row < R1; row += kWave) lbuf[row] = make_int2(kNeg, kNeg);
+            store_release(p.progress + task, kDone);
+            continue;
+        }
+        const bool prod_active = q > 0 && task_active(pr, band, q - 1, R);
+
+        WaveState<R> s;
+        const int M_rows = (int)max((int64_t)0, min((int64_t)R, pr.M - row0));
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int64_t row = row0 + k;
+            int code = kPadCode;
+            int h = NEGV, e = NEGV;
+            if (row < pr.M) {
+                code = acodes[row];
+                if (band == 0) {
+                    h = border_h(pr.left_kind, pr.left_open, p.ext, row + 1);
+                } else if (left_active) {
+                    const int2 lb = lbuf[row];
+                    h = lb.x;
+                    e = lb.y;
+                } else {
+                    h = kNeg;
+                    e = kNeg;
+                }
+            }
+            s.T[k] = row_table(code, p.match, p.mismatch);
+            s.H[k] = h;
+            s.E[k] = e;
+            s.HA[k] = h - p.open;
+            s.best[k] = LOCAL ? 0 : kNeg;
+            s.pos[k] = -1;
+        }
+        s.hup = 0;
+        s.hl = s.H[R - 1];
+        s.gl = NEGV;
+        // H(last row of this stripe, band's left column) for the stripe below.
+        if (lane == kWave - 1) my_slot[kSlotPad - 1] = make_int2(s.H[R - 1], 0);
+
+        // Last-row outputs (reconstruction halves): lane and sub-row of row M-1.
+        const bool has_out = pr.out_off >= 0 && q == pr.Q - 1;
+        if (has_out && band == 0 && lane == 0) {
+            const int h = border_h(pr.left_kind, pr.left_open, p.ext, pr.M);
+            p.out_h[pr.out_off] = h;
+            p.out_f[pr.out_off] = h;
+        }
+
+        // Inputs of a tick: the row above the stripe at band columns [base, base + 64).
+        auto fetch = [&](int base, int need) -> int2 {
+            const int rel = base + lane;
+            if (rel >= W) return make_int2(NEGV, NEGV);
+            if (q == 0) {
+                const int h = border_h(pr.top_kind, pr.top_open, p.ext, c0 + rel + 1);
+                if (pr.top_kind == BORDER_GAP) return make_int2(h, h - p.open);
+                return make_int2(h, LOCAL ? 0 : kNeg);
+            }
+            if (!prod_active) return make_int2(kNeg, kNeg);
+            wait_at_least(prod_prog, need, prod_seen);
+            return prod_slot[kSlotPad + rel];
+        };
+        {
+            int h_diag = 0;
+            if (q == 0) {
+                h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
+            } else {
+                wait_at_least(prod_prog, 1, prod_seen);
+                h_diag = prod_slot[kSlotPad - 1].x;
+            }
+            in_ring[0][lane] = fetch(0, min(kTick, W));
+            if (lane == 0) s.hup = h_diag;
+        }
+        __syncthreads();
+
+        TickCtx c;
+        c.out = out_buf;
+        c.lbuf = lbuf;
+        c.out_h = p.out_h;
+        c.out_f = p.out_f;
+        c.row0 = row0;
+        c.out_base = pr.out_off + c0 + 1;
+        c.lane = lane;
+        c.W = W;
+        c.M_rows = M_rows;
+        c.open = p.open;
+        c.ext = p.ext;
+        c.capture = capture;
+        c.out_lane = -1;
+        c.out_k = -1;
+        if (has_out) {
+            c.out_lane = (int)((pr.M - 1 - R0) / R);
+            c.out_k = (int)((pr.M - 1 - R0) % R);
+        }
+        unsigned long long pruned = 0;
+
+        for (int tau = 0; tau < n_ticks; ++tau) {
+            const int cur = tau & 1;
+            int2 nxt = make_int2(NEGV, NEGV);
+            if (tau + 1 < n_ticks) nxt = fetch(kTick * (tau + 1), min(kTick * (tau + 2), W));
+            const uint8_t* cols = bcodes + c0 + (int64_t)kTick * tau - lane;
+
+            const int gb = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int L = max(gb, pr.target);
+            const bool slow = (tau == 0) || has_out ||
+                              (capture && kTick * tau - (kTick - 1) <= W - 1 && W - 1 <= kTick * tau + (kTick - 1));
+            c.in = in_ring[cur];
+            c.col0 = c0 + (int64_t)kTick * tau;
+            c.rel0 = kTick * tau;
+
+            bool skip = false;
+            if (!slow) {
+                // diagonal band (global recurrence)
+                const int64_t dmax = c.col0 + (kTick - 1) - R0;
+                const int64_t dmin = c.col0 - R0 - (int64_t)kWave * R - (kTick - 2);
+                if (dmax < pr.d_lo || dmin > pr.d_hi) skip = true;
+                if (!skip && pr.prune) {
+                    int hm = max(s.hup, in_ring[cur][lane].x);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) hm = max(hm, s.H[k]);
+                    hm = wave_max(hm);
+                    if (LOCAL) hm = max(hm, 0);
+                    const int64_t rows_left = pr.M - R0;
+                    const int64_t cols_left = pr.N - (c.col0 - (kTick - 1));
+                    const int64_t ub = (int64_t)hm + (int64_t)p.match * min(rows_left, cols_left);
+                    skip = ub < (int64_t)L;
+                }
+            }
+
+            if (skip) {
+                pruned += (unsigned long long)kTick * kWave * R;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    s.H[k] = NEGV;
+                    s.E[k] = NEGV;
+                    s.HA[k] = NEGV - p.open;
+                }
+                s.hup = NEGV;
+                s.hl = NEGV;
+                s.gl = NEGV;
+                out_buf[lane] = make_int2(NEGV, NEGV);
+            } else {
+                int H0[R], E0[R], bstart[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    H0[k] = s.H[k];
+                    E0[k] = s.E[k];
+                    bstart[k] = s.best[k];
+                }
+                const int hup0 = s.hup, hl0 = s.hl, gl0 = s.gl;
+                bool want[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) want[k] = false;
+                if (slow) run_tick<R, LOCAL, false, true>(s, cols, c, want);
+                else run_tick<R, LOCAL, false, false>(s, cols, c, want);
+
+                if (pr.track) {
+                    bool any = false;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const bool inc = s.best[k] > bstart[k];
+                        want[k] = inc && s.best[k] >= L;
+                        if (inc) s.pos[k] = -1;
+                        any = any || want[k];
+                    }
+                    if (__any(any)) {
+                        // Replay from the snapshot; the replay ends in the same state.
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            s.H[k] = H0[k];
+                            s.E[k] = E0[k];
+                            s.HA[k] = H0[k] - p.open;
+                        }
+                        s.hup = hup0;
+                        s.hl = hl0;
+                        s.gl = gl0;
+                        if (slow) run_tick<R, LOCAL, true, true>(s, cols, c, want);
+                        else run_tick<R, LOCAL, true, false>(s, cols, c, want);
+                        int mx = kNeg;
+#pragma unroll
+                        for (int k = 0; k < R; ++k)
+                            if (want[k]) mx = max(mx, s.best[k]);
+                        mx = wave_max(mx);
+                        if (lane == 0 && mx > gb) atomicMax(gbest, mx);
+                    }
+                }
+            }
+
+            // Hand the 64 bottom-row columns of this tick to the stripe below.
+            __syncthreads();
+            {
+                const int rel = kTick * tau - (kTick - 1) + lane;
+                if (rel >= 0) my_slot[kSlotPad + rel] = out_buf[lane];
+            }
+            store_release(p.progress + task, min(kTick * tau + 1, W));
+            in_ring[cur ^ 1][lane] = nxt;
+            __syncthreads();
+        }
+
+        // Task record: the stripe's best value, its smallest row, that row's first column.
+        {
+            int bv = kNeg, bk = 0, bp = -1;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (k < M_rows && s.best[k] > bv) {
+                    bv = s.best[k];
+                    bk = k;
+                    bp = s.pos[k];
+                }
+            }
+            const int vmax = wave_max(bv);
+            const unsigned long long bal = __ballot(bv == vmax);
+            const int src = __ffsll((long long)bal) - 1;
+            const int rk = __shfl(bk, src);
+            const int rp = __shfl(bp, src);
+            if (lane == 0) {
+                TaskRec r;
+                r.score = vmax;
+                r.pad = 0;
+                r.row = R0 + (int64_t)src * R + rk;
+                r.col = rp;
+                p.recs[task] = r;
+                if (pruned) atomicAdd(p.pruned + pi, pruned);
+            }
+        }
+        store_release(p.progress + task, kDone);
+    }
+}
+
+// ------------------------------------------------------------------------ small kernels
+
+__device__ __forceinline__ uint8_t encode_letter(uint8_t ch, bool& ok) {
+    ch &= 0xDF;  // upper case
+    const uint8_t code = ch == 'A' ? 0 : ch == 'C' ? 1 : ch == 'G' ? 2 : ch == 'T' ? 3 : 0xff;
+    ok = code != 0xff;
+    return ok ? code : kPadCode;
+}
+
+__global__ void encode_kernel(const uint8_t* __restrict__ src, int64_t n, uint8_t* __restrict__ dst,
+                              int64_t pad_before, int64_t pad_after, int reverse, unsigned long long* bad) {
+    const int64_t total = pad_before + n + pad_after;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i - pad_before;
+        uint8_t code = kPadCode;
+        if (j >= 0 && j < n) {
+            const int64_t sj = reverse ? n - 1 - j : j;
+            bool ok;
+            code = encode_letter(src[sj], ok);
+            if (!ok) atomicMax(bad, (1ull << 62) - (unsigned long long)sj);  // largest value = first offset
+        }
+        dst[i] = code;
+    }
+}
+
+// Many sequences: sequence k is src[src_off[k] .. +len[k]) -> dst[dst_off[k] .. +len[k]).
+// Padding around the destinations is written by the caller (zero kernel + pad fill).
+__global__ void encode_many_kernel(const uint8_t* __restrict__ src, const int64_t* __restrict__ src_off,
+                                   const int64_t* __restrict__ dst_off, const int64_t* __restrict__ len,
+                                   int64_t n, uint8_t* __restrict__ dst, unsigned long long* bad) {
+    for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const int64_t so = src_off[k], d = dst_off[k], L = len[k];
+        for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
+            bool ok;
+            const uint8_t code = encode_letter(src[so + i], ok);
+            if (!ok) atomicMax(bad, (1ull << 62) - (unsigned long long)(so + i));
+            dst[d + i] = code;
+        }
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t words) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Per problem: best task record (highest score, then smallest row, then smallest column).
+__global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__ recs, const Prob* __restrict__ probs,
+                                                     int64_t n_probs, ScoreOut* out,
+                                                     const unsigned long long* __restrict__ pruned) {
+    __shared__ int32_t s_v[256];
+    __shared__ int64_t s_r[256];
+    __shared__ int64_t s_c[256];
+    const int t = threadIdx.x;
+    for (int64_t pi = blockIdx.x; pi < n_probs; pi += gridDim.x) {
+        const Prob pr = probs[pi];
+        const int64_t n = pr.Q * pr.n_bands;
+        int32_t bv = INT32_MIN;
+        int64_t br = INT64_MAX, bc = INT64_MAX;
+        for (int64_t i = t; i < n; i += blockDim.x) {
+            const TaskRec r = recs[pr.task0 + i];
+            const int64_t col = r.col < 0 ? INT64_MAX : r.col;
+            if (r.score > bv || (r.score == bv && (r.row < br || (r.row == br && col < bc)))) {
+                bv = r.score;
+                br = r.row;
+                bc = col;
+            }
+        }
+        s_v[t] = bv;
+        s_r[t] = br;
+        s_c[t] = bc;
+        __syncthreads();
+        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if (t < off) {
+                const int32_t v2 = s_v[t + off];
+                const int64_t r2 = s_r[t + off], c2 = s_c[t + off];
+                if (v2 > s_v[t] || (v2 == s_v[t] && (r2 < s_r[t] || (r2 == s_r[t] && c2 < s_c[t])))) {
+                    s_v[t] = v2;
+                    s_r[t] = r2;
+                    s_c[t] = c2;
+                }
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            ScoreOut o;
+            o.pruned_cells = pruned ? pruned[pi] : 0;
+            o.status = 0;
+            const bool local = pr.top_kind == BORDER_ZERO;
+            if (local && s_v[0] <= 0) {
+                o.score = 0;
+                o.end_a = -1;
+                o.end_b = -1;
+            } else {
+                o.score = s_v[0];
+                o.end_a = s_r[0];
+                o.end_b = s_c[0];
+                if (pr.track && (s_c[0] == INT64_MAX || s_c[0] >= pr.N || s_r[0] >= pr.M)) o.status = 1;
+            }
+            out[pi] = o;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------ launchers
+
+hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
+                         int reverse, unsigned long long* bad, hipStream_t st) {
+    const int64_t total = pad_before + n + pad_after;
+    const int blocks = (int)min((int64_t)4096, (total + 255) / 256);
+    hipLaunchKernelGGL(encode_kernel, dim3(max(blocks, 1)), dim3(256), 0, st, src, n, dst, pad_before, pad_after,
+                       reverse, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
+                              const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)min((int64_t)8192, n);
+    hipLaunchKernelGGL(encode_many_kernel, dim3(blocks), dim3(256), 0, st, src, src_off, dst_off, len, n, dst, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t st) {
+    if (!n) return hipSuccess;
+    const int blocks = (int)std::min((size_t)4096, (n + 255) / 256);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, (uint32_t)v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    return launch_fill_i32((int32_t*)p, 0, (bytes + 3) / 4, st);
+}
+
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, int grid, hipStream_t st) {
+    if (local) {
+        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true>), dim3(grid), dim3(kWave), 0, st, args);
+        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true>), dim3(grid), dim3(kWave), 0, st, args);
+        else return hipErrorInvalidValue;
+    } else {
+        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, false>), dim3(grid), dim3(kWave), 0, st, args);
+        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, false>), dim3(grid), dim3(kWave), 0, st, args);
+        else return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
+                         const unsigned long long* pruned, hipStream_t st) {
+    const int blocks = (int)min((int64_t)4096, max((int64_t)1, n_probs));
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, out, pruned);
+    return hipGetLastError();
+}
+
+}  // namespace swmi

@@ -5,7 +5,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "swmi.h"
+#include "swmi_internal.h"
 
 namespace swmi {
 
@@ -14,7 +17,7 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-enum { BUF_INPUT = 0, BUF_WORK = 1, BUF_AUX = 2, BUF_AUX2 = 3, BUF_COUNT = 4 };
+enum { BUF_INPUT = 0, BUF_WORK = 1, BUF_CODES = 2, BUF_OUT = 3, BUF_META = 4, BUF_COUNT = 5 };
 
 }  // namespace swmi
 
@@ -22,30 +25,66 @@ struct sw_context {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 0;
-    void* host_misc = nullptr;           // pinned 4 KiB for small device-to-host reads
+    void* host_misc = nullptr;           // pinned 64 KiB for small host<->device copies
+    size_t host_misc_bytes = 0;
     swmi::DevBuf bufs[swmi::BUF_COUNT];  // grow-only device buffers of the host-pointer API
 };
 
 namespace swmi {
 
-// Work decomposition and workspace layout of one score pass.
-struct ScorePlan {
-    int R;               // rows per lane
-    int grid;            // resident stripe waves (one wave per workgroup)
-    int64_t M, N, Q, W, n_bands, nslot, slot_stride;
-    size_t off_a, off_b, off_slots, off_lbuf, off_recs, off_zero, off_prog, off_misc;
-    size_t zero_bytes, total;
+// Host description of one DP problem (see Prob).
+struct ProbSpec {
+    int64_t a_off = 0, b_off = 0;  // into the launch's code buffers
+    int64_t M = 0, N = 0;
+    int32_t top_kind = BORDER_ZERO, left_kind = BORDER_ZERO;
+    int32_t top_open = 0, left_open = 0;
+    int32_t target = 0, prune = 0, track = 1;
+    int64_t d_lo = -kNoBand, d_hi = kNoBand;
+    int64_t out_off = -1;
 };
 
+// Decomposition and workspace layout of one engine launch.
+struct EnginePlan {
+    int R = 8;
+    int grid = 1;
+    bool local = true;
+    int64_t n_probs = 0, n_tasks = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;
+    std::vector<Prob> probs;
+    std::vector<int64_t> order;  // order[k] = index in the spec list of probs[k]
+    size_t off_probs = 0, off_slots = 0, off_lbuf = 0, off_recs = 0, off_outs = 0;
+    size_t off_zero = 0, off_prog = 0, off_gbest = 0, off_pruned = 0, off_misc = 0;
+    size_t zero_bytes = 0, total = 0;
+};
+
+// misc block (bytes from off_misc)
+enum { MISC_TICKET = 0, MISC_BAD_A = 16, MISC_BAD_B = 24, MISC_BYTES = 64 };
+constexpr unsigned long long kBadBase = 1ull << 62;
+
+size_t align_up(size_t v, size_t a);
 sw_status fail(sw_status st, const char* fmt, ...);
 sw_status ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out);
 sw_status check_scoring(const sw_scoring* s);
 sw_status check_lengths(int64_t la, int64_t lb, const sw_scoring* s);
 sw_status check_options(const sw_options* o);
-ScorePlan plan_score(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o);
-sw_status run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
-                    const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes, sw_score_result* out);
+
+// Plans a launch over `specs` (problems are reordered by decreasing cell count).
+// rows_per_lane / waves_per_cu / band_width: 0 = automatic.
+EnginePlan plan_engine(const sw_context* ctx, const std::vector<ProbSpec>& specs, bool local,
+                       int rows_per_lane, int waves_per_cu, int band_width);
+// Runs a planned launch inside workspace `ws` (plan.total bytes): clears the
+// counters, copies the table, launches the engine and the per-problem reduction
+// into the ScoreOut array at ws + plan.off_outs (ordered like plan.probs).
+sw_status run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
+                     const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f);
+// Copies `bytes` from device to the context's pinned buffer and waits for the stream.
+sw_status read_back(sw_context* ctx, const void* dev, size_t bytes, void** host);
+
 sw_status upload_pair(sw_context* ctx, const char* a, int64_t la, const char* b, int64_t lb, uint8_t** d_a,
                       uint8_t** d_b);
+
+// Score pass of one pair on device letters (workspace-driven; allocates nothing).
+size_t score_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o);
+sw_status run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
+                    const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes, sw_score_result* out);
 
 }  // namespace swmi

@@ -8,12 +8,40 @@ namespace swmi {
 
 constexpr int kWave = 64;          // wavefront width on gfx950
 constexpr int kTick = 64;          // steps a wave runs between boundary exchanges
-constexpr int kBPad = 128;         // code bytes before column 0 of the column sequence
+constexpr int kBPad = 128;         // code bytes before column 0 of every column sequence
 constexpr int kBPadTail = 256;     // code bytes after its last column
 constexpr int kSlotPad = 64;       // slot index of a band's first column
 constexpr uint8_t kPadCode = 4;    // column code that scores -128 against every row
 constexpr int32_t kDone = 0x7fffffff;
 constexpr uint32_t kPadTable = 0x80808080u;
+constexpr int32_t kNeg = -(1 << 30);  // minus infinity of the global recurrence
+constexpr int64_t kNoBand = (int64_t)1 << 62;
+
+// Border of a problem's DP matrix (row 0 or column 0).
+enum BorderKind : int32_t {
+    BORDER_ZERO = 0,  // local alignment: H = 0
+    BORDER_NEG = 1,   // anchored: H = -inf (the corner H(0,0) stays 0)
+    BORDER_GAP = 2    // a gap run from the corner: H = -(open_cost + ext * k)
+};
+
+// One DP problem of a launch.  Rows are the `a` codes, columns the `b` codes;
+// DP coordinates are 1-based (row 0 and column 0 are the borders).
+struct Prob {
+    int64_t a_off;       // first row code in the a-code buffer
+    int64_t b_off;       // column 0's code in the b-code buffer (padding around it)
+    int64_t M, N;
+    int64_t W, n_bands, Q;
+    int64_t task0;       // first ticket of this problem (problems are ticket-contiguous)
+    int64_t lbuf_off;    // first row of this problem in the band-boundary buffer
+    int64_t out_off;     // last-row outputs at out_h/out_f[out_off + j], j = 0..N; -1: none
+    int64_t d_lo, d_hi;  // diagonal band j - i kept by the global recurrence (kNoBand: all)
+    int32_t top_kind, left_kind;
+    int32_t top_open, left_open;  // gap-open cost of BORDER_GAP borders
+    int32_t target;      // tiles whose upper bound is below max(running best, target) are skipped
+    int32_t prune;       // 1 = skip tiles by that bound (exact; paper Section 2, pruning)
+    int32_t track;       // 1 = find the first cell of the best score (endpoint / start point)
+    int32_t pad_;
+};
 
 // One (band, stripe) task's best cell: value, then the smallest row holding it
 // in the stripe, then the first column of that row reaching it (-1 if not tracked).
@@ -24,26 +52,24 @@ struct TaskRec {
     int64_t col;
 };
 
-// Everything the forward local pass needs; device pointers.
-struct FwdArgs {
-    const uint8_t* a;        // row codes 0..3, length M
-    const uint8_t* b;        // column codes; b[-kBPad .. N + kBPadTail) readable, pads = kPadCode
-    int64_t M, N;
+struct EngineArgs {
+    const Prob* probs;
+    int64_t n_probs;
+    int64_t n_tasks;
+    const uint8_t* a_codes;
+    const uint8_t* b_codes;
     int32_t match, mismatch, open, ext;
-    int64_t Q;               // stripes (64 * R rows each)
-    int64_t W;               // band width in columns (multiple of 64)
-    int64_t n_bands;
-    int2* slots;             // nslot rows of slot_stride {H, g} pairs
+    int2* slots;             // nslot rows of slot_stride {H, gap} pairs
     int64_t slot_stride;
     int64_t nslot;
-    int32_t* progress;       // [n_bands * Q] columns published per task (kDone when finished)
-    uint32_t* ticket;        // task counter
-    int32_t* gbest;          // running lower bound on the best score
-    int2* lbuf;              // [M padded] {H, E} at the last column of the previous band
-    TaskRec* recs;           // [n_bands * Q]
-    unsigned long long* pruned_cells;  // cells skipped by pruning
-    int32_t prune;           // 0: none, 1: skip tiles that cannot reach max(gbest, threshold)
-    int32_t threshold;       // external lower bound T (0 = none)
+    int32_t* progress;       // [n_tasks] columns published (kDone when finished)
+    uint32_t* ticket;
+    int32_t* gbest;          // [n_probs] running best of each problem
+    int2* lbuf;              // {H, E} at the last column of the previous band, per row
+    TaskRec* recs;           // [n_tasks]
+    unsigned long long* pruned;  // [n_probs] cells skipped
+    int32_t* out_h;          // last-row H of problems with out_off >= 0
+    int32_t* out_f;          // last-row F (deletion-ending) of the same
 };
 
 struct ScoreOut {
@@ -53,10 +79,15 @@ struct ScoreOut {
     unsigned long long pruned_cells;
 };
 
-hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before,
-                         int64_t pad_after, unsigned long long* bad, hipStream_t st);
-hipError_t launch_fwd(const FwdArgs& args, int rows_per_lane, int grid, hipStream_t st);
-hipError_t launch_reduce(const TaskRec* recs, int64_t n, int64_t N, ScoreOut* out, hipStream_t st);
+hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
+                         int reverse, unsigned long long* bad, hipStream_t st);
+hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
+                              const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad,
+                              hipStream_t st);
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, int grid, hipStream_t st);
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
+                         const unsigned long long* pruned, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t st);
 
 }  // namespace swmi

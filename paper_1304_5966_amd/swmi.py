@@ -76,8 +76,16 @@ def _load():
     L.sw_batch.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64), ctypes.c_char_p,
                            ctypes.POINTER(i64), i32, ctypes.POINTER(Scoring), ctypes.POINTER(Options),
                            ctypes.POINTER(ScoreResult)]
+    L.sw_batch_workspace_size.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32,
+                                          ctypes.POINTER(Scoring), ctypes.POINTER(Options)]
+    L.sw_batch_workspace_size.restype = ctypes.c_size_t
+    L.sw_batch_dev.argtypes = [vp, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), i32,
+                               ctypes.POINTER(Scoring), ctypes.POINTER(Options), vp, ctypes.c_size_t,
+                               ctypes.POINTER(ScoreResult)]
+    L.sw_mm_host.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring), i32, i32,
+                             i32, i64, ctypes.c_char_p, i64, ctypes.POINTER(i64)]
     for name in ("sw_context_create", "sw_context_destroy", "sw_score", "sw_score_dev", "sw_align",
-                 "sw_start", "sw_batch"):
+                 "sw_start", "sw_batch", "sw_batch_dev", "sw_mm_host"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -86,7 +94,7 @@ lib = _load()
 
 EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy", "sw_score",
             "sw_score_workspace_size", "sw_score_dev", "sw_align", "sw_align_result_free", "sw_start",
-            "sw_batch")
+            "sw_batch", "sw_batch_workspace_size", "sw_batch_dev", "sw_mm_host")
 
 
 def _check(status: int):
@@ -207,6 +215,34 @@ class Context:
                             ctypes.byref(_options(**opts)), out))
         return [_score_of(out[i]) for i in range(n)]
 
+    def batch_dev(self, d_seqs_a, offs_a, d_seqs_b, offs_b, scoring=DEFAULT_SCORING, workspace=None,
+                  **opts):
+        """d_seqs_*: uint8 CUDA tensors of packed letters; offs_*: host int64 offsets (n + 1)."""
+        offs_a = np.ascontiguousarray(offs_a, dtype=np.int64)
+        offs_b = np.ascontiguousarray(offs_b, dtype=np.int64)
+        n = len(offs_a) - 1
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        sc, op = Scoring(*scoring), _options(**opts)
+        need = int(lib.sw_batch_workspace_size(self.handle, offs_a.ctypes.data_as(i64p),
+                                               offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc),
+                                               ctypes.byref(op)))
+        ws = workspace if workspace is not None else self.workspace(need)
+        out = (ScoreResult * max(n, 1))()
+        _check(lib.sw_batch_dev(self.handle, ctypes.c_void_p(d_seqs_a.data_ptr()),
+                                offs_a.ctypes.data_as(i64p), ctypes.c_void_p(d_seqs_b.data_ptr()),
+                                offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc), ctypes.byref(op),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), out))
+        return [_score_of(out[i]) for i in range(n)]
+
+    def batch_workspace_size(self, offs_a, offs_b, scoring=DEFAULT_SCORING, **opts) -> int:
+        offs_a = np.ascontiguousarray(offs_a, dtype=np.int64)
+        offs_b = np.ascontiguousarray(offs_b, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        return int(lib.sw_batch_workspace_size(self.handle, offs_a.ctypes.data_as(i64p),
+                                               offs_b.ctypes.data_as(i64p), len(offs_a) - 1,
+                                               ctypes.byref(Scoring(*scoring)),
+                                               ctypes.byref(_options(**opts))))
+
     # -- device-pointer entry point (torch-owned buffers, no allocation in the library)
     def workspace_size(self, len_a: int, len_b: int, **opts) -> int:
         return int(lib.sw_score_workspace_size(self.handle, len_a, len_b, ctypes.byref(_options(**opts))))
@@ -228,6 +264,18 @@ class Context:
                                 ctypes.byref(_options(**opts)), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), ctypes.byref(r)))
         return _score_of(r)
+
+
+def mm_host(a, b, scoring=DEFAULT_SCORING, tb=-1, te=-1, score=None) -> str:
+    """Host Myers-Miller of the whole of a x b (the reconstruction's CPU part)."""
+    a, b = _bytes(a), _bytes(b)
+    cap = 4 * (len(a) + len(b)) + 64
+    buf = ctypes.create_string_buffer(cap)
+    n = ctypes.c_int64()
+    _check(lib.sw_mm_host(a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)), tb, te,
+                          0 if score is None else 1, 0 if score is None else int(score), buf, cap,
+                          ctypes.byref(n)))
+    return buf.value.decode()
 
 
 def version() -> str:

@@ -1,0 +1,105 @@
+"""GPU start point and reconstruction (paper Section 2, second phase and
+Myers-Miller) against the CPU oracle: start coordinates and the canonical
+CIGAR must match bit for bit; every CIGAR rescored must give the score."""
+import numpy as np
+import pytest
+
+from paper_1304_5966_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1304_5966_amd import swmi
+    c = swmi.Context(0)
+    yield c
+    c.close()
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _key(al):
+    return (al.score, al.start_a, al.start_b, al.end_a, al.end_b, al.cigar)
+
+
+def test_start_point(ctx, orc):
+    rng = np.random.default_rng(21)
+    for t in range(16):
+        la, lb = int(rng.integers(1, 1500)), int(rng.integers(1, 1500))
+        p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.12) if t % 3 else \
+            synth.random_pair(int(rng.integers(1 << 30)), la, lb)
+        a, b = p.a.tobytes(), p.b.tobytes()
+        s, ea, eb = orc.sw_score(a, b)
+        _case(f"start {la}x{lb} S={s}")
+        if s == 0:
+            assert ctx.start(a, b, s, ea, eb) == (-1, -1)
+            continue
+        assert ctx.start(a, b, s, ea, eb) == orc.sw_start(a, b, s, ea, eb)
+
+
+def test_start_rejects_wrong_endpoint(ctx, orc):
+    from paper_1304_5966_amd import swmi
+    p = synth.homologous_pair(3, 600, 600, 0.1)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    s, ea, eb = orc.sw_score(a, b)
+    _case("start with an impossible score")
+    with pytest.raises(swmi.SwError):
+        ctx.start(a, b, s + 1, ea, eb)
+
+
+@pytest.mark.parametrize("div", [0.02, 0.1, 0.25])
+def test_align_small(ctx, orc, div):
+    rng = np.random.default_rng(int(div * 1000))
+    for t in range(10):
+        la, lb = int(rng.integers(1, 900)), int(rng.integers(1, 900))
+        p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, div)
+        a, b = p.a.tobytes(), p.b.tobytes()
+        _case(f"align {la}x{lb} div={div}")
+        got = ctx.align(a, b)
+        exp = orc.sw_align(a, b)
+        assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
+
+
+@pytest.mark.parametrize("la,lb,div", [(3000, 2900, 0.05), (5200, 4100, 0.1), (2500, 6000, 0.15)])
+def test_align_gpu_levels(ctx, orc, la, lb, div):
+    """Large enough that the top Myers-Miller levels run on the GPU."""
+    p = synth.homologous_pair(la * 7 + lb, la, lb, div)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    _case(f"align gpu levels {la}x{lb}")
+    got = ctx.align(a, b)
+    exp = orc.sw_align(a, b)
+    assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
+    assert orc.rescore(a, b, got.start_a, got.start_b, got.cigar) == (got.score, got.end_a, got.end_b)
+
+
+def test_align_degenerate(ctx, orc):
+    _case("align self")
+    a = synth.random_pair(5, 4000, 1).a.tobytes()
+    al = ctx.align(a, a)
+    assert (al.score, al.start_a, al.start_b, al.cigar) == (4000, 0, 0, "4000=")
+    _case("align empty / zero")
+    assert ctx.align(b"", b"ACGT").cigar == ""
+    z = ctx.align(b"AAAA", b"CCCC")
+    assert (z.score, z.start_a, z.end_a, z.cigar) == (0, -1, -1, "")
+    _case("align other scoring")
+    p = synth.homologous_pair(8, 2600, 2400, 0.1)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    for sc in [(2, 1, 3, 1), (1, 1, 2, 2)]:
+        got = ctx.align(a, b, scoring=sc)
+        exp = orc.sw_align(a, b, sc)
+        assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
+
+
+def test_align_config1(ctx, orc):
+    p = synth.config1()
+    a, b = p.a.tobytes(), p.b.tobytes()
+    _case("align config1")
+    got = ctx.align(a, b)
+    exp = orc.sw_align(a, b)
+    assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
