@@ -172,6 +172,45 @@ sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* 
                        const sw_options* options, void* d_workspace, size_t workspace_bytes,
                        sw_score_result* out);
 
+/* ---- Learned pruning threshold (not in the paper; see the pruning rule of
+ * Section 2, which it feeds).  A 256-128-128-1 ReLU network with BF16
+ * weights and inputs and FP32 accumulation predicts y = ln(1 + S) from pair
+ * features; the threshold is T = floor(0.9 * (exp(y) - 1)).  Parameters are one
+ * FP32 vector of sw_mlp_param_count() values: W1[256][128], b1[128],
+ * W2[128][128], b2[128], W3[128], b3 (row-major, input index first); the BF16
+ * copy (d_wbf) holds the same values rounded to nearest even.  All _dev calls
+ * take device pointers, run on the context's stream and allocate nothing. */
+
+/* Model file: "SWMLP001", int32 256, int32 128, float mean[256],
+ * float inv_std[256], float params[sw_mlp_param_count()].  sw_options.model. */
+sw_status sw_model_load(sw_context* ctx, const char* path, sw_model** out);
+sw_status sw_model_free(sw_model* model);
+int64_t sw_mlp_param_count(void);
+
+/* Features of pair p (letters d_seqs_a[offs_a[p]..offs_a[p+1]) and likewise b;
+ * offsets on the host) into d_out[p*256 .. p*256+256): [0,128) the
+ * complement-folded shared 4-mer spectrum, [128,254) ln(1 + number of
+ * 64-diagonal bands whose 12-mer hit count falls in each of 126 log bins),
+ * [254,256) ln|A| / ln 4e6 and ln|B| / ln 4e6. */
+size_t sw_features_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b, int32_t n_pairs);
+sw_status sw_features_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* offs_a, const uint8_t* d_seqs_b,
+                          const int64_t* offs_b, int32_t n_pairs, float* d_out, void* d_workspace,
+                          size_t workspace_bytes);
+/* d_x[n][256] (BF16) = round((d_feat - mean) * inv_std). */
+sw_status sw_mlp_standardize_dev(sw_context* ctx, const float* d_feat, int32_t n, const float* d_mean,
+                                 const float* d_inv_std, uint16_t* d_x);
+/* Forward pass: h1, h2 [n][128] (post-ReLU, BF16-rounded, stored as float), y [n]. */
+sw_status sw_mlp_forward_dev(sw_context* ctx, const uint16_t* d_x, int32_t n, const uint16_t* d_wbf,
+                             const float* d_params, float* d_h1, float* d_h2, float* d_y);
+/* Gradient of mean((y - target)^2) over the n samples into d_grad (same layout
+ * as the parameters); d_scratch holds 64 + 257 * n floats.  Fixed summation order. */
+sw_status sw_mlp_backward_dev(sw_context* ctx, const uint16_t* d_x, int32_t n, const uint16_t* d_wbf,
+                              const float* d_h1, const float* d_h2, const float* d_y, const float* d_target,
+                              float* d_scratch, float* d_grad);
+/* One Adam step (bias-corrected, step >= 1) on the FP32 parameters; refreshes d_wbf. */
+sw_status sw_mlp_adam_dev(sw_context* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad,
+                          int32_t step, float lr, float beta1, float beta2, float eps, uint16_t* d_wbf);
+
 #ifdef __cplusplus
 }
 #endif

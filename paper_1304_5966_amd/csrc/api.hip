@@ -288,15 +288,21 @@ static size_t codes_bytes(int64_t M, int64_t N) {
     return align_up((size_t)M + 64, 256) + align_up((size_t)(kBPad + N + kBPadTail), 256) + 256;
 }
 
+static bool uses_model(const sw_options* o) {
+    return o && o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0;
+}
+
 size_t swmi::score_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o) {
     const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
                                      o ? o->waves_per_cu : 0, o ? o->band_width : 0);
-    return codes_bytes(M, N) + p.total;
+    size_t total = codes_bytes(M, N) + p.total;
+    if (uses_model(o)) total = std::max(total, predict_workspace_size(M, N, 1));
+    return total;
 }
 
-sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
-                          const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
-                          sw_score_result* out) {
+static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
+                                const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
+                                sw_score_result* out) {
     const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
                                      o ? o->waves_per_cu : 0, o ? o->band_width : 0);
     const size_t need = codes_bytes(M, N) + p.total;
@@ -330,6 +336,38 @@ sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const 
     out->threshold = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
     const unsigned long long total = (unsigned long long)M * (unsigned long long)N;
     out->cells_computed = (int64_t)(so.pruned_cells >= total ? 0 : total - so.pruned_cells);
+    return SW_OK;
+}
+
+// LEARNED mode: T from the model (or the caller), one pass that skips tiles below
+// max(running best, T); if the best found is below T the result is not known to
+// be optimal and the pass reruns with the running best alone (exact).
+sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
+                          const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
+                          sw_score_result* out) {
+    if (!o || o->prune_mode != SW_PRUNE_LEARNED) return run_score_once(ctx, d_a, M, d_b, N, sc, o, ws, ws_bytes, out);
+    sw_options ol = *o;
+    if (ol.threshold == 0) {
+        if (!ol.model) return fail(SW_EINVAL, "SW_PRUNE_LEARNED needs a model or a threshold");
+        const int64_t oa[2] = {0, M}, ob[2] = {0, N};
+        std::vector<int32_t> T;
+        sw_status st = predict_thresholds(ctx, ol.model, d_a, oa, d_b, ob, 1, ws, ws_bytes, T);
+        if (st != SW_OK) return st;
+        ol.threshold = T[0];
+    }
+    sw_status st = run_score_once(ctx, d_a, M, d_b, N, sc, &ol, ws, ws_bytes, out);
+    if (st != SW_OK) return st;
+    out->threshold = ol.threshold;
+    if (out->score < ol.threshold) {
+        const int64_t first = out->cells_computed;
+        sw_options ob = ol;
+        ob.prune_mode = SW_PRUNE_BEST;
+        ob.threshold = 0;
+        if ((st = run_score_once(ctx, d_a, M, d_b, N, sc, &ob, ws, ws_bytes, out)) != SW_OK) return st;
+        out->threshold = ol.threshold;
+        out->fallback = 1;
+        out->cells_computed += first;
+    }
     return SW_OK;
 }
 

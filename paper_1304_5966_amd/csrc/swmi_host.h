@@ -19,6 +19,13 @@ struct DevBuf {
 
 enum { BUF_INPUT = 0, BUF_WORK = 1, BUF_CODES = 2, BUF_OUT = 3, BUF_META = 4, BUF_COUNT = 5 };
 
+// Learned thresholds (mlp.hip): workspace for n pairs of at most (M, N) letters, and
+// T = floor(0.9 * predicted score) per pair from device letters.
+size_t predict_workspace_size(int64_t max_M, int64_t max_N, int32_t n);
+sw_status predict_thresholds(sw_context* ctx, const sw_model* m, const uint8_t* d_a, const int64_t* offs_a,
+                             const uint8_t* d_b, const int64_t* offs_b, int32_t n, void* ws, size_t ws_bytes,
+                             std::vector<int32_t>& T);
+
 }  // namespace swmi
 
 struct sw_context {
@@ -86,5 +93,12 @@ sw_status upload_pair(sw_context* ctx, const char* a, int64_t la, const char* b,
 size_t score_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o);
 sw_status run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
                     const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes, sw_score_result* out);
+
+// Learned thresholds (mlp.hip): workspace for n pairs of at most (M, N) letters, and
+// T = floor(0.9 * predicted score) per pair from device letters.
+size_t predict_workspace_size(int64_t max_M, int64_t max_N, int32_t n);
+sw_status predict_thresholds(sw_context* ctx, const sw_model* m, const uint8_t* d_a, const int64_t* offs_a,
+                             const uint8_t* d_b, const int64_t* offs_b, int32_t n, void* ws, size_t ws_bytes,
+                             std::vector<int32_t>& T);
 
 }  // namespace swmi

@@ -84,8 +84,22 @@ def _load():
                                ctypes.POINTER(ScoreResult)]
     L.sw_mm_host.argtypes = [ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring), i32, i32,
                              i32, i64, ctypes.c_char_p, i64, ctypes.POINTER(i64)]
+    L.sw_model_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.sw_model_free.argtypes = [vp]
+    L.sw_mlp_param_count.restype = i64
+    L.sw_features_workspace_size.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32]
+    L.sw_features_workspace_size.restype = ctypes.c_size_t
+    L.sw_features_dev.argtypes = [vp, vp, ctypes.POINTER(i64), vp, ctypes.POINTER(i64), i32, vp, vp,
+                                  ctypes.c_size_t]
+    L.sw_mlp_standardize_dev.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.sw_mlp_forward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    L.sw_mlp_backward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.sw_mlp_adam_dev.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, vp]
     for name in ("sw_context_create", "sw_context_destroy", "sw_score", "sw_score_dev", "sw_align",
-                 "sw_start", "sw_batch", "sw_batch_dev", "sw_mm_host"):
+                 "sw_start", "sw_batch", "sw_batch_dev", "sw_mm_host", "sw_model_load", "sw_model_free",
+                 "sw_features_dev", "sw_mlp_standardize_dev", "sw_mlp_forward_dev", "sw_mlp_backward_dev",
+                 "sw_mlp_adam_dev"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -94,7 +108,9 @@ lib = _load()
 
 EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy", "sw_score",
             "sw_score_workspace_size", "sw_score_dev", "sw_align", "sw_align_result_free", "sw_start",
-            "sw_batch", "sw_batch_workspace_size", "sw_batch_dev", "sw_mm_host")
+            "sw_batch", "sw_batch_workspace_size", "sw_batch_dev", "sw_mm_host", "sw_model_load",
+            "sw_model_free", "sw_mlp_param_count", "sw_features_workspace_size", "sw_features_dev",
+            "sw_mlp_standardize_dev", "sw_mlp_forward_dev", "sw_mlp_backward_dev", "sw_mlp_adam_dev")
 
 
 def _check(status: int):
@@ -264,6 +280,86 @@ class Context:
                                 ctypes.byref(_options(**opts)), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), ctypes.byref(r)))
         return _score_of(r)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Model:
+    """A threshold model file loaded for SW_PRUNE_LEARNED (pass ``model=m.handle``)."""
+
+    def __init__(self, ctx: "Context", path: str):
+        h = ctypes.c_void_p()
+        _check(lib.sw_model_load(ctx.handle, path.encode(), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib.sw_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def param_count() -> int:
+    return int(lib.sw_mlp_param_count())
+
+
+def features_dev(ctx: "Context", d_a, offs_a, d_b, offs_b, out=None):
+    """Features [n, 256] (float32 CUDA tensor) of packed device letters with host offsets."""
+    torch = ctx._torch
+    offs_a = np.ascontiguousarray(offs_a, dtype=np.int64)
+    offs_b = np.ascontiguousarray(offs_b, dtype=np.int64)
+    n = len(offs_a) - 1
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    need = int(lib.sw_features_workspace_size(ctx.handle, offs_a.ctypes.data_as(i64p),
+                                              offs_b.ctypes.data_as(i64p), n))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=d_a.device)
+    if out is None:
+        out = torch.empty((n, 256), dtype=torch.float32, device=d_a.device)
+    _check(lib.sw_features_dev(ctx.handle, _ptr(d_a), offs_a.ctypes.data_as(i64p), _ptr(d_b),
+                               offs_b.ctypes.data_as(i64p), n, _ptr(out), _ptr(ws), ws.numel()))
+    return out
+
+
+def mlp_standardize(ctx, d_feat, d_mean, d_inv_std):
+    torch = ctx._torch
+    n = d_feat.shape[0]
+    x = torch.empty((n, 256), dtype=torch.int16, device=d_feat.device)
+    _check(lib.sw_mlp_standardize_dev(ctx.handle, _ptr(d_feat), n, _ptr(d_mean), _ptr(d_inv_std), _ptr(x)))
+    return x
+
+
+def mlp_forward(ctx, d_x, d_wbf, d_params):
+    """d_x: int16 [n, 256] holding BF16 bits; returns (y [n], h1 [n,128], h2 [n,128]) float32."""
+    torch = ctx._torch
+    n = d_x.shape[0]
+    h1 = torch.empty((n, 128), dtype=torch.float32, device=d_x.device)
+    h2 = torch.empty((n, 128), dtype=torch.float32, device=d_x.device)
+    y = torch.empty(n, dtype=torch.float32, device=d_x.device)
+    _check(lib.sw_mlp_forward_dev(ctx.handle, _ptr(d_x), n, _ptr(d_wbf), _ptr(d_params), _ptr(h1), _ptr(h2),
+                                  _ptr(y)))
+    return y, h1, h2
+
+
+def mlp_backward(ctx, d_x, d_wbf, h1, h2, y, target):
+    torch = ctx._torch
+    n = d_x.shape[0]
+    scratch = torch.empty(64 + 257 * n, dtype=torch.float32, device=d_x.device)
+    grad = torch.empty(param_count(), dtype=torch.float32, device=d_x.device)
+    _check(lib.sw_mlp_backward_dev(ctx.handle, _ptr(d_x), n, _ptr(d_wbf), _ptr(h1), _ptr(h2), _ptr(y),
+                                   _ptr(target), _ptr(scratch), _ptr(grad)))
+    return grad
+
+
+def mlp_adam(ctx, d_params, d_m, d_v, d_grad, step, lr, d_wbf, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib.sw_mlp_adam_dev(ctx.handle, _ptr(d_params), _ptr(d_m), _ptr(d_v), _ptr(d_grad), int(step),
+                               float(lr), float(beta1), float(beta2), float(eps), _ptr(d_wbf)))
 
 
 def mm_host(a, b, scoring=DEFAULT_SCORING, tb=-1, te=-1, score=None) -> str:
