@@ -70,7 +70,9 @@ def main():
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the pruned, batched and learned legs")
+    ap.add_argument("--learned-pairs", type=int, default=6)
+    ap.add_argument("--seq-sample", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the score pass is "
@@ -145,10 +147,111 @@ def main():
         assert r.key() == score, (r, score)
         line["pruned_best"] = {"gcups_eff": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 3),
                                "cells_computed_frac": round(r.cells_computed / cells, 4)}
+        line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample)
+        line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(pair)
     print(json.dumps(line), flush=True)
+
+
+def _pack(pairs):
+    import numpy as np
+    a = np.concatenate([p.a for p in pairs])
+    b = np.concatenate([p.b for p in pairs])
+    oa = np.concatenate(([0], np.cumsum([p.a.size for p in pairs]))).astype(np.int64)
+    ob = np.concatenate(([0], np.cumsum([p.b.size for p in pairs]))).astype(np.int64)
+    return a, oa, b, ob
+
+
+def batched_leg(ctx, torch, swmi, synth, seq_sample):
+    """20 000 pairs (100-20 000 bp, half homologous) in one launch vs one call per pair."""
+    log("batched leg: generating 20 000 pairs")
+    pairs = synth.config3()
+    a, oa, b, ob = _pack(pairs)
+    d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    cells = sum(p.cells for p in pairs)
+    ws = ctx.workspace(ctx.batch_workspace_size(oa, ob))
+    ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws)
+    dt = time.perf_counter() - t0
+    # the same pairs, one score call each (a seeded sample of the pairs, scaled)
+    import numpy as np
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(len(pairs), size=min(seq_sample, len(pairs)), replace=False))
+    sample_cells = sum(pairs[i].cells for i in idx)
+    dev_pairs = [(torch.from_numpy(pairs[i].a).cuda(), torch.from_numpy(pairs[i].b).cuda()) for i in idx]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq = [ctx.score_dev(x, y) for x, y in dev_pairs]
+    dts = time.perf_counter() - t1
+    for k, i in enumerate(idx):
+        assert seq[k].key() == res[i].key(), (i, seq[k], res[i])
+    log(f"batched: {cells / dt / 1e9:.1f} GCUPS; per-pair calls: {sample_cells / dts / 1e9:.1f} GCUPS")
+    return {"workload": "20 000 pairs, lengths log-uniform 100-20 000 bp per side, even pairs homologous "
+                        "(divergence 5-30 %), odd pairs unrelated; one persistent launch",
+            "gcups": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 2), "cells": cells,
+            "per_pair_calls_gcups": round(sample_cells / dts / 1e9, 2),
+            "per_pair_sample": int(len(idx)),
+            "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2)}
+
+
+def learned_leg(ctx, torch, swmi, synth, n_pairs):
+    """Learned threshold vs no pruning vs running-best pruning on 1-4 Mbp pairs."""
+    import numpy as np
+    path = os.path.join(ROOT, "paper_1304_5966_amd", "models", "threshold_mlp.bin")
+    if not os.path.exists(path) or n_pairs <= 0:
+        return {"status": "no trained model in the tree"}
+    model = swmi.Model(ctx, path)
+    log(f"learned leg: {n_pairs} pairs of 1-4 Mbp")
+    # a seeded subset of the evaluation seed's 2 000 pairs, homologous ones first
+    pairs = []
+    i = 0
+    while len(pairs) < n_pairs and i < 2000:
+        p = synth.config4_pair(i)
+        if p.homologous or len(pairs) >= n_pairs // 2:
+            pairs.append(p)
+        i += 1
+    a, oa, b, ob = _pack(pairs)
+    d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    cells = sum(p.cells for p in pairs)
+    out = {"workload": f"{len(pairs)} pairs of the 2 000-pair learned-pruning set (1-4 Mbp per side; "
+                       f"first homologous pairs of the evaluation seed, then the next pairs)",
+           "cells": cells}
+    ref = None
+    for name, kw in (("none", dict(prune=swmi.PRUNE_NONE)), ("best", dict(prune=swmi.PRUNE_BEST)),
+                     ("learned", dict(prune=swmi.PRUNE_LEARNED, model=model.handle))):
+        ws = ctx.workspace(ctx.batch_workspace_size(oa, ob, **kw))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws, **kw)
+        dt = time.perf_counter() - t0
+        keys = [r.key() for r in res]
+        if ref is None:
+            ref = keys
+        assert keys == ref, name
+        out[name] = {"gcups_eff": round(cells / dt / 1e9, 2), "s": round(dt, 3),
+                     "cells_computed_frac": round(sum(r.cells_computed for r in res) / cells, 4)}
+        if name == "learned":
+            out[name]["miss_rate"] = round(float(np.mean([r.fallback for r in res])), 4)
+        log(f"learned leg {name}: {cells / dt / 1e9:.1f} GCUPS")
+    # ceiling: threshold equal to the true score
+    best = [r[0] for r in ref]
+    t0 = time.perf_counter()
+    tot = 0
+    for k, p in enumerate(pairs):
+        r = ctx.score_dev(d_a[oa[k]:oa[k + 1]], d_b[ob[k]:ob[k + 1]], prune=swmi.PRUNE_LEARNED,
+                          threshold=max(best[k], 1))
+        assert r.key() == ref[k]
+        tot += r.cells_computed
+    dt = time.perf_counter() - t0
+    out["oracle_threshold"] = {"gcups_eff": round(cells / dt / 1e9, 2), "s": round(dt, 3),
+                               "cells_computed_frac": round(tot / cells, 4)}
+    out["speedup_learned_vs_none"] = round(out["none"]["s"] / out["learned"]["s"], 3)
+    model.close()
+    return out
 
 
 if __name__ == "__main__":

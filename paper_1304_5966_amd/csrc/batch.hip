@@ -35,37 +35,40 @@ struct BatchLayout {
     EnginePlan plan;
 };
 
-sw_status make_layout(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b, int32_t n,
-                      const sw_scoring* sc, const sw_options* o, BatchLayout& L) {
-    if (n < 0) return fail(SW_EINVAL, "sw_batch: n_pairs < 0");
-    if (n > 0 && (!offs_a || !offs_b)) return fail(SW_EINVAL, "sw_batch: NULL offsets");
-    int64_t bpos = 0;
+// Pairs given as (start, length) into the packed device letters; T: per-pair
+// thresholds (LEARNED mode) or null.
+sw_status make_layout(sw_context* ctx, const std::vector<int64_t>& as, const std::vector<int64_t>& al,
+                      const std::vector<int64_t>& bs, const std::vector<int64_t>& bl, const sw_scoring* sc,
+                      const sw_options* o, const std::vector<int32_t>* T, BatchLayout& L) {
+    const int32_t n = (int32_t)as.size();
+    int64_t apos = 0, bpos = 0;
     for (int32_t p = 0; p < n; ++p) {
-        const int64_t la = offs_a[p + 1] - offs_a[p], lb = offs_b[p + 1] - offs_b[p];
+        const int64_t la = al[(size_t)p], lb = bl[(size_t)p];
         if (la < 0 || lb < 0) return fail(SW_EINVAL, "sw_batch: offsets of pair %d decrease", p);
         sw_status st = check_lengths(la, lb, sc);
         if (st != SW_OK) return st;
-        L.a_src.push_back(offs_a[p]);
-        L.a_dst.push_back(offs_a[p] - offs_a[0]);
+        L.a_src.push_back(as[(size_t)p]);
+        L.a_dst.push_back(apos);
         L.a_len.push_back(la);
-        L.b_src.push_back(offs_b[p]);
+        L.b_src.push_back(bs[(size_t)p]);
         L.b_dst.push_back(bpos + kBPad);
         L.b_len.push_back(lb);
         if (la > 0 && lb > 0) {
             ProbSpec s;
-            s.a_off = offs_a[p] - offs_a[0];
+            s.a_off = apos;
             s.b_off = bpos + kBPad;
             s.M = la;
             s.N = lb;
             s.prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
-            s.target = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
+            s.target = T ? (*T)[(size_t)p] : ((o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0);
             s.track = 1;
             L.specs.push_back(s);
             L.pair_of_spec.push_back(p);
         }
+        apos += la;
         bpos += kBPad + lb + kBPadTail;
     }
-    L.a_bytes = n ? offs_a[n] - offs_a[0] : 0;
+    L.a_bytes = apos;
     L.b_bytes = bpos;
     L.plan = plan_engine(ctx, L.specs, true, o ? o->rows_per_lane : 0, o ? o->waves_per_cu : 0,
                          o ? o->band_width : 0);
@@ -136,12 +139,118 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
 
 }  // namespace
 
+static sw_status pairs_of(const int64_t* offs_a, const int64_t* offs_b, int32_t n, std::vector<int64_t>& as,
+                          std::vector<int64_t>& al, std::vector<int64_t>& bs, std::vector<int64_t>& bl) {
+    if (n < 0) return fail(SW_EINVAL, "sw_batch: n_pairs < 0");
+    if (n > 0 && (!offs_a || !offs_b)) return fail(SW_EINVAL, "sw_batch: NULL offsets");
+    for (int32_t p = 0; p < n; ++p) {
+        as.push_back(offs_a[p]);
+        al.push_back(offs_a[p + 1] - offs_a[p]);
+        bs.push_back(offs_b[p]);
+        bl.push_back(offs_b[p + 1] - offs_b[p]);
+    }
+    return SW_OK;
+}
+
+static bool batch_uses_model(const sw_options* o) {
+    return o && o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0;
+}
+
 extern "C" size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b,
                                           int32_t n_pairs, const sw_scoring* scoring, const sw_options* options) {
     if (!ctx || !scoring) return 0;
+    std::vector<int64_t> as, al, bs, bl;
+    if (pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl) != SW_OK) return 0;
     BatchLayout L;
-    if (make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L) != SW_OK) return 0;
-    return L.total;
+    if (make_layout(ctx, as, al, bs, bl, scoring, options, nullptr, L) != SW_OK) return 0;
+    size_t total = L.total;
+    if (batch_uses_model(options)) {
+        int64_t mM = 0, mN = 0;
+        for (size_t k = 0; k < al.size(); ++k) {
+            mM = std::max(mM, al[k]);
+            mN = std::max(mN, bl[k]);
+        }
+        total = std::max(total, predict_workspace_size(mM, mN, n_pairs));
+    }
+    return total;
+}
+
+// Batched pass; in LEARNED mode with a model: thresholds first, then one pass,
+// then the pairs whose best fell below their threshold again with the running
+// best alone (exact), flagged as fallbacks.
+static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, const std::vector<int64_t>& as,
+                           const std::vector<int64_t>& al, const std::vector<int64_t>& bs,
+                           const std::vector<int64_t>& bl, const sw_scoring* sc, const sw_options* o, void* ws,
+                           size_t ws_bytes, sw_score_result* out) {
+    const int32_t n = (int32_t)as.size();
+    std::vector<int32_t> T;
+    if (batch_uses_model(o)) {
+        if (!o->model) return fail(SW_EINVAL, "SW_PRUNE_LEARNED needs a model or a threshold");
+        std::vector<int64_t> oa((size_t)n + 1), ob((size_t)n + 1);
+        // predict_thresholds takes offsets of consecutive pairs: pass per-pair starts via
+        // a one-pair call each when pairs are not contiguous
+        bool contiguous = true;
+        for (int32_t p = 0; p + 1 < n; ++p)
+            if (as[(size_t)p] + al[(size_t)p] != as[(size_t)p + 1] || bs[(size_t)p] + bl[(size_t)p] != bs[(size_t)p + 1])
+                contiguous = false;
+        if (contiguous && n > 0) {
+            for (int32_t p = 0; p < n; ++p) {
+                oa[(size_t)p] = as[(size_t)p];
+                ob[(size_t)p] = bs[(size_t)p];
+            }
+            oa[(size_t)n] = as[(size_t)n - 1] + al[(size_t)n - 1];
+            ob[(size_t)n] = bs[(size_t)n - 1] + bl[(size_t)n - 1];
+            sw_status st = predict_thresholds(ctx, o->model, d_a, oa.data(), d_b, ob.data(), n, ws, ws_bytes, T);
+            if (st != SW_OK) return st;
+        } else {
+            T.assign((size_t)n, 0);
+            for (int32_t p = 0; p < n; ++p) {
+                const int64_t a2[2] = {as[(size_t)p], as[(size_t)p] + al[(size_t)p]};
+                const int64_t b2[2] = {bs[(size_t)p], bs[(size_t)p] + bl[(size_t)p]};
+                std::vector<int32_t> t1;
+                sw_status st = predict_thresholds(ctx, o->model, d_a, a2, d_b, b2, 1, ws, ws_bytes, t1);
+                if (st != SW_OK) return st;
+                T[(size_t)p] = t1[0];
+            }
+        }
+    }
+    BatchLayout L;
+    sw_status st = make_layout(ctx, as, al, bs, bl, sc, o, T.empty() ? nullptr : &T, L);
+    if (st != SW_OK) return st;
+    if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out)) != SW_OK) return st;
+    if (!o || o->prune_mode != SW_PRUNE_LEARNED) return SW_OK;
+    std::vector<int64_t> as2, al2, bs2, bl2;
+    std::vector<int32_t> idx;
+    for (int32_t p = 0; p < n; ++p) {
+        const int32_t t = T.empty() ? o->threshold : T[(size_t)p];
+        out[p].threshold = t;
+        if (out[p].score < t && al[(size_t)p] > 0 && bl[(size_t)p] > 0) {
+            idx.push_back(p);
+            as2.push_back(as[(size_t)p]);
+            al2.push_back(al[(size_t)p]);
+            bs2.push_back(bs[(size_t)p]);
+            bl2.push_back(bl[(size_t)p]);
+        }
+    }
+    if (idx.empty()) return SW_OK;
+    sw_options ob2 = *o;
+    ob2.prune_mode = SW_PRUNE_BEST;
+    ob2.threshold = 0;
+    BatchLayout L2;
+    if ((st = make_layout(ctx, as2, al2, bs2, bl2, sc, &ob2, nullptr, L2)) != SW_OK) return st;
+    if (L2.total > ws_bytes) return fail(SW_ENOMEM, "batch fallback: workspace too small");
+    std::vector<sw_score_result> r2(idx.size());
+    if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data())) != SW_OK) return st;
+    for (size_t k = 0; k < idx.size(); ++k) {
+        sw_score_result& r = out[idx[k]];
+        const int64_t first = r.cells_computed;
+        const int32_t t = r.threshold;
+        r = r2[k];
+        r.cells_computed += first;
+        r.threshold = t;
+        r.fallback = 1;
+    }
+    return SW_OK;
 }
 
 extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* offs_a,
@@ -152,12 +261,12 @@ extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, cons
     sw_status st;
     if ((st = check_scoring(scoring)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
-    BatchLayout L;
-    if ((st = make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L)) != SW_OK) return st;
+    std::vector<int64_t> as, al, bs, bl;
+    if ((st = pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl)) != SW_OK) return st;
     if (n_pairs > 0 && (!d_seqs_a || !d_seqs_b)) return fail(SW_EINVAL, "sw_batch_dev: NULL sequences");
-    if (!L.specs.empty() && !d_workspace) return fail(SW_EINVAL, "sw_batch_dev: NULL workspace");
+    if (n_pairs > 0 && !d_workspace) return fail(SW_EINVAL, "sw_batch_dev: NULL workspace");
     HIP_TRY(hipSetDevice(ctx->device));
-    return run_batch(ctx, d_seqs_a, d_seqs_b, n_pairs, scoring, L, d_workspace, workspace_bytes, out);
+    return batch_all(ctx, d_seqs_a, d_seqs_b, as, al, bs, bl, scoring, options, d_workspace, workspace_bytes, out);
 }
 
 extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t* offs_a, const char* seqs_b,
@@ -167,24 +276,25 @@ extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t
     sw_status st;
     if ((st = check_scoring(scoring)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
-    BatchLayout L;
-    if ((st = make_layout(ctx, offs_a, offs_b, n_pairs, scoring, options, L)) != SW_OK) return st;
+    std::vector<int64_t> as, al, bs, bl;
+    if ((st = pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl)) != SW_OK) return st;
     if (n_pairs == 0) return SW_OK;
-    if ((L.a_bytes && !seqs_a) || (L.b_bytes && !seqs_b)) return fail(SW_EINVAL, "sw_batch: NULL sequences");
-    HIP_TRY(hipSetDevice(ctx->device));
-    // the letters are uploaded at their own offsets: device index = host offset - offs[0]
-    void* in;
     const int64_t na = offs_a[n_pairs] - offs_a[0], nb = offs_b[n_pairs] - offs_b[0];
+    if ((na && !seqs_a) || (nb && !seqs_b)) return fail(SW_EINVAL, "sw_batch: NULL sequences");
+    if (na < 0 || nb < 0) return fail(SW_EINVAL, "sw_batch: offsets decrease");
+    HIP_TRY(hipSetDevice(ctx->device));
+    void* in;
     if ((st = ctx_buffer(ctx, BUF_INPUT, align_up((size_t)na + 1, 256) + (size_t)nb + 256, &in)) != SW_OK)
         return st;
     uint8_t* d_a = (uint8_t*)in;
     uint8_t* d_b = d_a + align_up((size_t)na + 1, 256);
     if (na) HIP_TRY(hipMemcpyAsync(d_a, seqs_a + offs_a[0], (size_t)na, hipMemcpyHostToDevice, ctx->stream));
     if (nb) HIP_TRY(hipMemcpyAsync(d_b, seqs_b + offs_b[0], (size_t)nb, hipMemcpyHostToDevice, ctx->stream));
-    // make_layout uses absolute offsets for the sources; shift them to the uploaded copy
-    for (auto& v : L.a_src) v -= offs_a[0];
-    for (auto& v : L.b_src) v -= offs_b[0];
+    for (auto& v : as) v -= offs_a[0];
+    for (auto& v : bs) v -= offs_b[0];
+    const size_t need = sw_batch_workspace_size(ctx, offs_a, offs_b, n_pairs, scoring, options);
+    if (!need) return fail(SW_EINTERNAL, "sw_batch: workspace size");
     void* ws;
-    if ((st = ctx_buffer(ctx, BUF_WORK, L.total, &ws)) != SW_OK) return st;
-    return run_batch(ctx, d_a, d_b, n_pairs, scoring, L, ws, L.total, out);
+    if ((st = ctx_buffer(ctx, BUF_WORK, need, &ws)) != SW_OK) return st;
+    return batch_all(ctx, d_a, d_b, as, al, bs, bl, scoring, options, ws, need, out);
 }

@@ -62,20 +62,38 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-__device__ __forceinline__ int load_acquire(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Stripe-to-stripe hand-off.  Boundary values and column counts are accessed
+// with relaxed atomics at agent scope, which the hardware serves coherently
+// across CUs and XCDs without cache maintenance.  Ordering: the producer waits
+// for its boundary stores to complete (vmcnt 0) before storing the count; the
+// consumer reads boundary values only after reading a sufficient count.
+__device__ __forceinline__ int2 ld_shared_i2(const int2* p) {
+    const unsigned long long v =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
 }
 
-__device__ __forceinline__ void store_release(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_shared_i2(int2* p, int2 v) {
+    const unsigned long long w = (unsigned long long)(uint32_t)v.x | ((unsigned long long)(uint32_t)v.y << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until *flag >= need; `seen` caches the last value read with acquire semantics.
+__device__ __forceinline__ int load_count(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void publish_count(int32_t* p, int32_t v) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until *flag >= need; `seen` caches the last value read.
 __device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need, int32_t& seen) {
     while (seen < need) {
-        seen = load_acquire(flag);
+        seen = load_count(flag);
         if (seen < need) __builtin_amdgcn_s_sleep(1);
     }
+    asm volatile("" ::: "memory");
 }
 
 __device__ __forceinline__ uint32_t row_table(int code, int match, int mismatch) {
@@ -176,7 +194,7 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
                         s.HA[k] = HAn;
                     }
                     if (!TRACK && c.capture && rel == c.W - 1 && k < c.M_rows)
-                        c.lbuf[c.row0 + k] = make_int2(Hn, En);
+                        st_shared_i2(c.lbuf + c.row0 + k, make_int2(Hn, En));
                 } else {
                     s.H[k] = Hn;
                     s.E[k] = En;
@@ -264,8 +282,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             if (lane == 0) {
                 int hlast = kNeg;
                 if (band == 0) hlast = border_h(pr.left_kind, pr.left_open, p.ext, R1);
-                else if (left_active) hlast = lbuf[R1 - 1].x;
-                my_slot[kSlotPad - 1] = make_int2(hlast, 0);
+                else if (left_active) hlast = ld_shared_i2(lbuf + R1 - 1).x;
+                st_shared_i2(my_slot + kSlotPad - 1, make_int2(hlast, 0));
                 TaskRec r;
                 r.score = kNeg;
                 r.pad = 0;
@@ -274,8 +292,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 p.recs[task] = r;
             }
             if (capture)
-                for (int64_t row = R0 + lane; row < R1; row += kWave) lbuf[row] = make_int2(kNeg, kNeg);
-            store_release(p.progress + task, kDone);
+                for (int64_t row = R0 + lane; row < R1; row += kWave) st_shared_i2(lbuf + row, make_int2(kNeg, kNeg));
+            publish_count(p.progress + task, kDone);
             continue;
         }
         const bool prod_active = q > 0 && task_active(pr, band, q - 1, R);
@@ -292,7 +310,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 if (band == 0) {
                     h = border_h(pr.left_kind, pr.left_open, p.ext, row + 1);
                 } else if (left_active) {
-                    const int2 lb = lbuf[row];
+                    const int2 lb = ld_shared_i2(lbuf + row);
                     h = lb.x;
                     e = lb.y;
                 } else {
@@ -311,7 +329,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
         s.hl = s.H[R - 1];
         s.gl = NEGV;
         // H(last row of this stripe, band's left column) for the stripe below.
-        if (lane == kWave - 1) my_slot[kSlotPad - 1] = make_int2(s.H[R - 1], 0);
+        if (lane == kWave - 1) st_shared_i2(my_slot + kSlotPad - 1, make_int2(s.H[R - 1], 0));
 
         // Last-row outputs (reconstruction halves): lane and sub-row of row M-1.
         const bool has_out = pr.out_off >= 0 && q == pr.Q - 1;
@@ -332,7 +350,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             }
             if (!prod_active) return make_int2(kNeg, kNeg);
             wait_at_least(prod_prog, need, prod_seen);
-            return prod_slot[kSlotPad + rel];
+            return ld_shared_i2(prod_slot + kSlotPad + rel);
         };
         {
             int h_diag = 0;
@@ -340,7 +358,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
             } else {
                 wait_at_least(prod_prog, 1, prod_seen);
-                h_diag = prod_slot[kSlotPad - 1].x;
+                h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
             }
             in_ring[0][lane] = fetch(0, min(kTick, W));
             if (lane == 0) s.hup = h_diag;
@@ -409,7 +427,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                     s.E[k] = NEGV;
                     s.HA[k] = NEGV - p.open;
                 }
-                s.hup = NEGV;
+                // lane 0's next diagonal is the row above at this tick's last column,
+                // which lies outside the skipped tile
+                s.hup = lane == 0 ? in_ring[cur][kTick - 1].x : NEGV;
                 s.hl = NEGV;
                 s.gl = NEGV;
                 out_buf[lane] = make_int2(NEGV, NEGV);
@@ -464,9 +484,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             __syncthreads();
             {
                 const int rel = kTick * tau - (kTick - 1) + lane;
-                if (rel >= 0) my_slot[kSlotPad + rel] = out_buf[lane];
+                if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, out_buf[lane]);
             }
-            store_release(p.progress + task, min(kTick * tau + 1, W));
+            publish_count(p.progress + task, min(kTick * tau + 1, W));
             in_ring[cur ^ 1][lane] = nxt;
             __syncthreads();
         }
@@ -497,7 +517,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 if (pruned) atomicAdd(p.pruned + pi, pruned);
             }
         }
-        store_release(p.progress + task, kDone);
+        publish_count(p.progress + task, kDone);
     }
 }
 
@@ -599,7 +619,10 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
                 o.score = s_v[0];
                 o.end_a = s_r[0];
                 o.end_b = s_c[0];
-                if (pr.track && (s_c[0] == INT64_MAX || s_c[0] >= pr.N || s_r[0] >= pr.M)) o.status = 1;
+                // cells are tracked from max(running best, target) up: below the target
+                // (a learned threshold above the best) the endpoint is unknown by design
+                if (pr.track && s_v[0] >= pr.target && (s_c[0] == INT64_MAX || s_c[0] >= pr.N || s_r[0] >= pr.M))
+                    o.status = 1;
             }
             out[pi] = o;
         }
