@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rows-per-lane", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (shape 8 rows/lane, 8 waves/CU)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the pruned, batched and learned legs")
     ap.add_argument("--learned-pairs", type=int, default=6)
@@ -119,6 +120,13 @@ def main():
     d_b = torch.from_numpy(pair.b).to(dev)
     ctx = swmi.Context(0)
     opts = dict(rows_per_lane=args.rows_per_lane, waves_per_cu=args.waves_per_cu)
+    tune = None
+    if not (args.no_tune or args.rows_per_lane or args.waves_per_cu):
+        from paper_1304_5966_amd import autotune
+        log("autotuning the engine shape on the leading 2 Mbp x 2 Mbp of the pair")
+        tune = {"sample": "leading 2 Mbp x 2 Mbp of the pair", "candidates": []}
+        tune["chosen"] = autotune.tune_score(ctx, d_a, d_b, crop=2_000_000, use_cache=False, log=log,
+                                             table=tune["candidates"])
     ws = ctx.workspace(ctx.workspace_size(M, N, **opts))
     stream = torch.cuda.current_stream(dev)
 
@@ -165,7 +173,11 @@ def main():
                      "peak": round(VALU_PEAK / 1e12, 3), "unit": "Tops/s int32",
                      "frac": round(achieved / VALU_PEAK, 4), "traffic": profiled_traffic(),
                      "ops_per_cell": OPS_PER_CELL, "kernel_ms": round(gpu_ms, 3)},
+        "engine_shape": tune["chosen"] if tune else {"rows_per_lane": args.rows_per_lane or 8,
+                                                      "waves_per_cu": args.waves_per_cu or 8},
     }
+    if tune:
+        line["autotune"] = tune
     if not args.no_extra:
         log("pruned pass")
         r = ctx.score_dev(d_a, d_b, workspace=ws, prune=swmi.PRUNE_BEST, **opts)
@@ -176,7 +188,7 @@ def main():
         assert r.key() == score, (r, score)
         line["pruned_best"] = {"gcups_eff": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 3),
                                "cells_computed_frac": round(r.cells_computed / cells, 4)}
-        line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample)
+        line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)
         line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
     if not args.no_cpu:
         log("cpu baseline")
@@ -193,19 +205,38 @@ def _pack(pairs):
     return a, oa, b, ob
 
 
-def batched_leg(ctx, torch, swmi, synth, seq_sample):
+def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     """20 000 pairs (100-20 000 bp, half homologous) in one launch vs one call per pair."""
     log("batched leg: generating 20 000 pairs")
     pairs = synth.config3()
     a, oa, b, ob = _pack(pairs)
     d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
     cells = sum(p.cells for p in pairs)
+    table = []
+    shape = None
+    if tune:
+        from paper_1304_5966_amd import autotune
+        shape = autotune.tune_batch(ctx, d_a, oa, d_b, ob, use_cache=False, log=log, table=table)
     ws = ctx.workspace(ctx.batch_workspace_size(oa, ob))
     ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws)
     dt = time.perf_counter() - t0
+    # the same launch captured as a HIP graph on a context bound to its own stream
+    gstream = torch.cuda.Stream()
+    gctx = swmi.Context(0, stream=gstream)
+    if shape:
+        gctx.set_tuning(swmi.TUNE_BATCH, shape["rows_per_lane"], shape["waves_per_cu"])
+    gws = torch.empty(gctx.batch_workspace_size(oa, ob, graph=True), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    gres = gctx.batch_dev(d_a, oa, d_b, ob, workspace=gws, graph=True)   # capture + first replay
+    t2 = time.perf_counter()
+    gres = gctx.batch_dev(d_a, oa, d_b, ob, workspace=gws, graph=True)
+    dtg = time.perf_counter() - t2
+    assert [r.key() for r in gres] == [r.key() for r in res]
+    gctx.close()
+    del gws
     # the same pairs, one score call each (a seeded sample of the pairs, scaled)
     import numpy as np
     rng = np.random.default_rng(1)
@@ -224,7 +255,9 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample):
             "gcups": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 2), "cells": cells,
             "per_pair_calls_gcups": round(sample_cells / dts / 1e9, 2),
             "per_pair_sample": int(len(idx)),
-            "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2)}
+            "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2),
+            "graph_replay_gcups": round(cells / dtg / 1e9, 2), "graph_replay_ms": round(dtg * 1000, 2),
+            "engine_shape": shape, "autotune_candidates": table}
 
 
 def learned_leg(ctx, torch, swmi, synth, n_pairs):

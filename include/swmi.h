@@ -77,11 +77,16 @@ typedef struct {
     int32_t prune_mode;        /* sw_prune_mode */
     int32_t threshold;         /* > 0: use this T instead of the model's prediction (LEARNED mode) */
     const sw_model* model;     /* LEARNED mode: threshold model (sw_model_load) */
-    int32_t rows_per_lane;     /* 0 = autotuned; else 4, 8 or 16 */
-    int32_t waves_per_cu;      /* 0 = autotuned; else 1..16 resident stripe waves per CU */
+    int32_t rows_per_lane;     /* 0 = the context's tuned value (else 8); else 4 or 8 */
+    int32_t waves_per_cu;      /* 0 = the context's tuned value (else 8); else 1..16 stripe waves per CU */
     int32_t band_width;        /* 0 = automatic; else columns per band, a positive multiple of 64 */
-    int32_t flags;             /* reserved, 0 */
+    int32_t flags;             /* SW_FLAG_* bits */
 } sw_options;
+
+/* sw_batch_dev: capture the device work of the call in a HIP graph and replay
+ * it on later calls with the same pairs, pointers, workspace and options (the
+ * context keeps one graph).  Capture needs a non-null stream. */
+#define SW_FLAG_GRAPH 1
 
 typedef struct {
     int32_t score;             /* best local score S >= 0 */
@@ -115,6 +120,26 @@ const char* sw_version(void);
  * workspace and tuning; it is not thread-safe: use one per stream. */
 sw_status sw_context_create(int device, void* hip_stream, sw_context** out);
 sw_status sw_context_destroy(sw_context* ctx);
+
+/* Engine shape per workload class, set by a tuner that timed the candidates
+ * on the device.  Calls whose options leave rows_per_lane / waves_per_cu at 0
+ * take the class's tuned value (8 / 8 when untuned).  The class of a launch
+ * follows its mean cell count per DP problem: HUGE from 1e12, LARGE from
+ * 1e10, below that BATCH when the launch holds more than one problem and
+ * SMALL when it holds one.  Workspace sizes depend on
+ * the shape: query them after changing the tuning.
+ * rows_per_lane: 0 (untuned), 4 or 8; waves_per_cu: 0 (untuned) or 1..16. */
+typedef enum {
+    SW_TUNE_PAIR_SMALL = 0,
+    SW_TUNE_PAIR_LARGE = 1,
+    SW_TUNE_PAIR_HUGE = 2,
+    SW_TUNE_BATCH = 3
+} sw_tune_class;
+
+sw_status sw_context_set_tuning(sw_context* ctx, int32_t tune_class, int32_t rows_per_lane,
+                                int32_t waves_per_cu);
+sw_status sw_context_get_tuning(const sw_context* ctx, int32_t tune_class, int32_t* rows_per_lane,
+                                int32_t* waves_per_cu);
 
 /* First phase (paper Section 2): best local score and its endpoint.
  * a[0..len_a), b[0..len_b): host letters.  out: caller-owned. */

@@ -76,7 +76,26 @@ extern "C" sw_status sw_context_destroy(sw_context* ctx) {
     else (void)hipDeviceSynchronize();
     for (auto& b : ctx->bufs) (void)hipFree(b.ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     delete ctx;
+    return SW_OK;
+}
+
+extern "C" sw_status sw_context_set_tuning(sw_context* ctx, int32_t cls, int32_t R, int32_t wpc) {
+    if (!ctx) return fail(SW_EINVAL, "null context");
+    if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
+    if (R != 0 && R != 4 && R != 8) return fail(SW_EINVAL, "rows_per_lane must be 0, 4 or 8 (got %d)", R);
+    if (wpc < 0 || wpc > 16) return fail(SW_EINVAL, "waves_per_cu must be 0..16 (got %d)", wpc);
+    ctx->tuned_R[cls] = R;
+    ctx->tuned_wpc[cls] = wpc;
+    return SW_OK;
+}
+
+extern "C" sw_status sw_context_get_tuning(const sw_context* ctx, int32_t cls, int32_t* R, int32_t* wpc) {
+    if (!ctx || !R || !wpc) return fail(SW_EINVAL, "null argument");
+    if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
+    *R = ctx->tuned_R[cls];
+    *wpc = ctx->tuned_wpc[cls];
     return SW_OK;
 }
 
@@ -140,6 +159,7 @@ sw_status swmi::check_options(const sw_options* o) {
     if (o->waves_per_cu < 0 || o->waves_per_cu > 16)
         return fail(SW_EINVAL, "waves_per_cu must be 0..16 (got %d)", o->waves_per_cu);
     if (o->threshold < 0) return fail(SW_EINVAL, "threshold must be >= 0");
+    if (o->flags & ~SW_FLAG_GRAPH) return fail(SW_EINVAL, "unknown flags 0x%x", o->flags);
     if (o->band_width < 0 || o->band_width % kTick)
         return fail(SW_EINVAL, "band_width must be 0 or a positive multiple of 64 (got %d)", o->band_width);
     return SW_OK;
@@ -151,8 +171,16 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
                              int rows_per_lane, int waves_per_cu, int band_width) {
     EnginePlan p;
     p.local = local;
-    p.R = rows_per_lane ? rows_per_lane : 8;
-    const int wpc = waves_per_cu ? waves_per_cu : 8;
+    double cells = 0;
+    for (const auto& s : specs) cells += (double)s.M * (double)s.N;
+    const double per = specs.empty() ? 0.0 : cells / (double)specs.size();
+    const int cls = per >= 1e12                      ? SW_TUNE_PAIR_HUGE
+                    : per >= 1e10                    ? SW_TUNE_PAIR_LARGE
+                    : specs.size() > 1               ? SW_TUNE_BATCH
+                                                     : SW_TUNE_PAIR_SMALL;
+    const int tR = ctx->tuned_R[cls], tW = ctx->tuned_wpc[cls];
+    p.R = rows_per_lane ? rows_per_lane : tR ? tR : 8;
+    const int wpc = waves_per_cu ? waves_per_cu : tW ? tW : 8;
     const int64_t rows_per_stripe = (int64_t)kWave * p.R;
     // Largest-first order keeps the long problems from trailing the launch.
     std::vector<size_t> order(specs.size());
@@ -236,13 +264,19 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     return p;
 }
 
-sw_status swmi::run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
-                           const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f) {
+sw_status swmi::upload_engine_table(sw_context* ctx, const EnginePlan& plan, void* ws) {
+    HIP_TRY(hipMemcpyAsync((uint8_t*)ws + plan.off_probs, plan.probs.data(), (size_t)plan.n_probs * sizeof(Prob),
+                           hipMemcpyHostToDevice, ctx->stream));
+    return SW_OK;
+}
+
+// Kernel launches only (capturable in a HIP graph: no copies, no memsets).
+sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes,
+                                      const uint8_t* b_codes, const sw_scoring* sc, void* ws, int32_t* out_h,
+                                      int32_t* out_f) {
     uint8_t* base = (uint8_t*)ws;
     hipStream_t st = ctx->stream;
     HIP_TRY(launch_zero(base + plan.off_zero, plan.zero_bytes, st));
-    HIP_TRY(hipMemcpyAsync(base + plan.off_probs, plan.probs.data(), (size_t)plan.n_probs * sizeof(Prob),
-                           hipMemcpyHostToDevice, st));
     EngineArgs a{};
     a.probs = (const Prob*)(base + plan.off_probs);
     a.n_probs = plan.n_probs;
@@ -267,6 +301,13 @@ sw_status swmi::run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_
     HIP_TRY(launch_engine(a, plan.R, plan.local, plan.grid, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.pruned, st));
     return SW_OK;
+}
+
+sw_status swmi::run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
+                           const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f) {
+    sw_status st = upload_engine_table(ctx, plan, ws);
+    if (st != SW_OK) return st;
+    return launch_engine_kernels(ctx, plan, a_codes, b_codes, sc, ws, out_h, out_f);
 }
 
 // ------------------------------------------------------------------------ score pass

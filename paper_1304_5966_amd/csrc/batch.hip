@@ -87,8 +87,27 @@ sw_status make_layout(sw_context* ctx, const std::vector<int64_t>& as, const std
     return SW_OK;
 }
 
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+// Device work of one batch (capturable): pads, encodes, engine, reduction.
+sw_status batch_device_work(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
+                            BatchLayout& L, uint8_t* base) {
+    hipStream_t s = ctx->stream;
+    int64_t* tab = (int64_t*)(base + L.off_tab);
+    unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
+    HIP_TRY(launch_zero(base + L.off_flags, 256, s));
+    HIP_TRY(launch_fill_i32((int32_t*)(base + L.off_b), 0x04040404, (size_t)(L.b_bytes + 64 + 3) / 4, s));
+    HIP_TRY(launch_encode_many(d_a, tab, tab + n, tab + 2 * (size_t)n, n, base + L.off_a, bad, s));
+    HIP_TRY(launch_encode_many(d_b, tab + 3 * (size_t)n, tab + 4 * (size_t)n, tab + 5 * (size_t)n, n,
+                               base + L.off_b, bad + 1, s));
+    return launch_engine_kernels(ctx, L.plan, base + L.off_a, base + L.off_b, sc, base + L.off_eng, nullptr, nullptr);
+}
+
 sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
-                    BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out) {
+                    BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out, bool graph) {
     if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
     for (int32_t p = 0; p < n; ++p) {
         std::memset(&out[p], 0, sizeof out[p]);
@@ -105,16 +124,53 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
     std::copy(L.b_src.begin(), L.b_src.end(), h_tab.begin() + 3 * (size_t)n);
     std::copy(L.b_dst.begin(), L.b_dst.end(), h_tab.begin() + 4 * (size_t)n);
     std::copy(L.b_len.begin(), L.b_len.end(), h_tab.begin() + 5 * (size_t)n);
+    // tables go in before every launch (also before a graph replay)
     HIP_TRY(hipMemcpyAsync(tab, h_tab.data(), h_tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_zero(base + L.off_flags, 256, s));
-    HIP_TRY(launch_fill_i32((int32_t*)(base + L.off_b), 0x04040404, (size_t)(L.b_bytes + 64 + 3) / 4, s));
-    unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
-    HIP_TRY(launch_encode_many(d_a, tab, tab + n, tab + 2 * (size_t)n, n, base + L.off_a, bad, s));
-    HIP_TRY(launch_encode_many(d_b, tab + 3 * (size_t)n, tab + 4 * (size_t)n, tab + 5 * (size_t)n, n,
-                               base + L.off_b, bad + 1, s));
-    uint8_t* eng = base + L.off_eng;
-    sw_status st = run_engine(ctx, L.plan, base + L.off_a, base + L.off_b, sc, eng, nullptr, nullptr);
+    sw_status st = upload_engine_table(ctx, L.plan, base + L.off_eng);
     if (st != SW_OK) return st;
+    if (graph) {
+        if (!s) return fail(SW_EINVAL, "SW_FLAG_GRAPH needs a context bound to a non-null stream");
+        uint64_t key = 0x51ed270b7f4a7c15ull;
+        for (uint64_t v : {(uint64_t)(uintptr_t)d_a, (uint64_t)(uintptr_t)d_b, (uint64_t)(uintptr_t)ws, (uint64_t)n,
+                           (uint64_t)L.plan.n_probs, (uint64_t)L.plan.n_tasks, (uint64_t)L.plan.grid,
+                           (uint64_t)L.plan.R, (uint64_t)L.plan.nslot, (uint64_t)L.plan.slot_stride,
+                           (uint64_t)L.plan.total, (uint64_t)L.plan.local, (uint64_t)L.plan.off_slots,
+                           (uint64_t)L.plan.off_lbuf, (uint64_t)L.plan.off_recs, (uint64_t)L.plan.off_outs,
+                           (uint64_t)L.plan.off_zero, (uint64_t)L.plan.zero_bytes, (uint64_t)L.plan.off_gbest,
+                           (uint64_t)L.plan.off_pruned, (uint64_t)L.plan.off_misc, (uint64_t)L.off_a,
+                           (uint64_t)L.off_b, (uint64_t)L.off_tab, (uint64_t)L.off_flags, (uint64_t)L.off_eng,
+                           (uint64_t)L.total, (uint64_t)L.a_bytes, (uint64_t)L.b_bytes,
+                           (uint64_t)sc->match, (uint64_t)sc->mismatch, (uint64_t)sc->gap_open,
+                           (uint64_t)sc->gap_extend})
+            key = mix(key, v);
+        if (!ctx->graph_exec || ctx->graph_key != key) {
+            if (ctx->graph_exec) {
+                HIP_TRY(hipGraphExecDestroy(ctx->graph_exec));
+                ctx->graph_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            st = batch_device_work(ctx, d_a, d_b, n, sc, L, base);
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (st != SW_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SW_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ctx->graph_exec = nullptr;
+                return fail(SW_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            ctx->graph_key = key;
+        }
+        HIP_TRY(hipGraphLaunch(ctx->graph_exec, s));
+    } else {
+        if ((st = batch_device_work(ctx, d_a, d_b, n, sc, L, base)) != SW_OK) return st;
+    }
+    uint8_t* eng = base + L.off_eng;
+    unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
     std::vector<ScoreOut> so((size_t)L.plan.n_probs);
     unsigned long long flags[2];
     HIP_TRY(hipMemcpyAsync(flags, bad, sizeof flags, hipMemcpyDeviceToHost, s));
@@ -123,16 +179,16 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
     if (flags[0]) return fail(SW_EINVAL, "seqs_a: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[0]);
     if (flags[1]) return fail(SW_EINVAL, "seqs_b: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[1]);
     for (size_t k = 0; k < so.size(); ++k) {
-        const int32_t p = L.pair_of_spec[(size_t)L.plan.order[k]];
+        const size_t spec = (size_t)L.plan.order[k];
+        const int32_t p = L.pair_of_spec[spec];
         if (so[k].status) return fail(SW_EINTERNAL, "batch: endpoint of pair %d was not tracked", p);
         sw_score_result& r = out[p];
         r.score = so[k].score;
         r.end_a = so[k].end_a;
         r.end_b = so[k].end_b;
-        const unsigned long long cells =
-            (unsigned long long)L.specs[(size_t)L.plan.order[k]].M * (unsigned long long)L.specs[(size_t)L.plan.order[k]].N;
+        const unsigned long long cells = (unsigned long long)L.specs[spec].M * (unsigned long long)L.specs[spec].N;
         r.cells_computed = (int64_t)(so[k].pruned_cells >= cells ? 0 : cells - so[k].pruned_cells);
-        r.threshold = L.specs[(size_t)L.plan.order[k]].target;
+        r.threshold = L.specs[spec].target;
     }
     return SW_OK;
 }
@@ -217,7 +273,8 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
     BatchLayout L;
     sw_status st = make_layout(ctx, as, al, bs, bl, sc, o, T.empty() ? nullptr : &T, L);
     if (st != SW_OK) return st;
-    if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out)) != SW_OK) return st;
+    const bool graph = o && (o->flags & SW_FLAG_GRAPH);
+    if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out, graph)) != SW_OK) return st;
     if (!o || o->prune_mode != SW_PRUNE_LEARNED) return SW_OK;
     std::vector<int64_t> as2, al2, bs2, bl2;
     std::vector<int32_t> idx;
@@ -240,7 +297,8 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
     if ((st = make_layout(ctx, as2, al2, bs2, bl2, sc, &ob2, nullptr, L2)) != SW_OK) return st;
     if (L2.total > ws_bytes) return fail(SW_ENOMEM, "batch fallback: workspace too small");
     std::vector<sw_score_result> r2(idx.size());
-    if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data())) != SW_OK) return st;
+    if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data(), false)) != SW_OK)
+        return st;
     for (size_t k = 0; k < idx.size(); ++k) {
         sw_score_result& r = out[idx[k]];
         const int64_t first = r.cells_computed;

@@ -154,18 +154,26 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
     const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
     uint32_t lo = src[0], hi = src[1];
-#pragma unroll 1
+    // lane 0's inputs are read one 4-step group ahead (the ring holds 64 + 4 entries)
+    const int4* in4 = reinterpret_cast<const int4*>(c.in);
+    int4 nx0 = in4[0], nx1 = in4[1];
+    constexpr int kUnroll = (SLOW || TRACK) ? 1 : 2;  // the hot path renames its carried registers
+#pragma unroll kUnroll
     for (int g = 0; g < kTick / 4; ++g) {
         const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
         lo = hi;
         hi = src[g + 2];
+        const int2 ins[4] = {make_int2(nx0.x, nx0.y), make_int2(nx0.z, nx0.w), make_int2(nx1.x, nx1.y),
+                             make_int2(nx1.z, nx1.w)};
+        nx0 = in4[2 * g + 2];
+        nx1 = in4[2 * g + 3];
         uint32_t sc[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, s.T[k], cw);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = 4 * g + i;
-            const int2 in = c.in[m];
+            const int2 in = ins[i];
             const int upH = dpp_shr1(in.x, s.hl);
             const int upG = dpp_shr1(in.y, s.gl);
             int diag = s.hup;
@@ -229,7 +237,7 @@ __device__ __forceinline__ bool task_active(const Prob& pr, int64_t band, int64_
 template <int R, bool LOCAL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void engine_kernel(
     EngineArgs p) {
-    __shared__ int2 in_ring[2][kTick];
+    __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
     __shared__ int2 out_buf[kTick];
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
     const int lane = threadIdx.x;

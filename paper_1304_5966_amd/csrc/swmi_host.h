@@ -32,6 +32,12 @@ struct sw_context {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 0;
+    // captured batch launch (SW_FLAG_GRAPH): replayed while the key matches
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    // autotuned shapes per workload class (0 = not tuned): rows per lane, waves per CU
+    int tuned_R[4] = {0, 0, 0, 0};
+    int tuned_wpc[4] = {0, 0, 0, 0};
     void* host_misc = nullptr;           // pinned 64 KiB for small host<->device copies
     size_t host_misc_bytes = 0;
     swmi::DevBuf bufs[swmi::BUF_COUNT];  // grow-only device buffers of the host-pointer API
@@ -83,6 +89,10 @@ EnginePlan plan_engine(const sw_context* ctx, const std::vector<ProbSpec>& specs
 // into the ScoreOut array at ws + plan.off_outs (ordered like plan.probs).
 sw_status run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
                      const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f);
+sw_status upload_engine_table(sw_context* ctx, const EnginePlan& plan, void* ws);
+sw_status launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes,
+                                const uint8_t* b_codes, const sw_scoring* sc, void* ws, int32_t* out_h,
+                                int32_t* out_f);
 // Copies `bytes` from device to the context's pinned buffer and waits for the stream.
 sw_status read_back(sw_context* ctx, const void* dev, size_t bytes, void** host);
 

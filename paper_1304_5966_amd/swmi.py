@@ -12,11 +12,17 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# torch first: libswmi.so and torch share the HIP runtime library
+# (libamdhip64.so.7), and the process must bind to torch's copy so that torch
+# streams and allocations are valid inside the library.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libswmi.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EUNSUPPORTED, SW_EINTERNAL = 0, -1, -2, -3, -4, -5
 PRUNE_NONE, PRUNE_BEST, PRUNE_LEARNED = 0, 1, 2
+TUNE_PAIR_SMALL, TUNE_PAIR_LARGE, TUNE_PAIR_HUGE, TUNE_BATCH = 0, 1, 2, 3
+FLAG_GRAPH = 1  # SW_FLAG_GRAPH
 DEFAULT_SCORING = (1, 3, 5, 2)
 
 
@@ -61,6 +67,8 @@ def _load():
     L.sw_version.restype = ctypes.c_char_p
     L.sw_context_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.sw_context_destroy.argtypes = [vp]
+    L.sw_context_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.sw_context_get_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sw_score.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring),
                            ctypes.POINTER(Options), ctypes.POINTER(ScoreResult)]
     L.sw_score_workspace_size.argtypes = [vp, i64, i64, ctypes.POINTER(Options)]
@@ -96,7 +104,8 @@ def _load():
     L.sw_mlp_backward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.sw_mlp_adam_dev.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, vp]
-    for name in ("sw_context_create", "sw_context_destroy", "sw_score", "sw_score_dev", "sw_align",
+    for name in ("sw_context_create", "sw_context_destroy", "sw_context_set_tuning",
+                 "sw_context_get_tuning", "sw_score", "sw_score_dev", "sw_align",
                  "sw_start", "sw_batch", "sw_batch_dev", "sw_mm_host", "sw_model_load", "sw_model_free",
                  "sw_features_dev", "sw_mlp_standardize_dev", "sw_mlp_forward_dev", "sw_mlp_backward_dev",
                  "sw_mlp_adam_dev"):
@@ -106,7 +115,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy", "sw_score",
+EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy",
+            "sw_context_set_tuning", "sw_context_get_tuning", "sw_score",
             "sw_score_workspace_size", "sw_score_dev", "sw_align", "sw_align_result_free", "sw_start",
             "sw_batch", "sw_batch_workspace_size", "sw_batch_dev", "sw_mm_host", "sw_model_load",
             "sw_model_free", "sw_mlp_param_count", "sw_features_workspace_size", "sw_features_dev",
@@ -127,9 +137,9 @@ def _bytes(x) -> bytes:
 
 
 def _options(prune=PRUNE_NONE, threshold=0, rows_per_lane=0, waves_per_cu=0, band_width=0,
-             model=None) -> Options:
+             model=None, graph=False) -> Options:
     return Options(int(prune), int(threshold), model, int(rows_per_lane), int(waves_per_cu),
-                   int(band_width), 0)
+                   int(band_width), FLAG_GRAPH if graph else 0)
 
 
 @dataclass
@@ -184,6 +194,14 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, tune_class: int, rows_per_lane: int, waves_per_cu: int):
+        _check(lib.sw_context_set_tuning(self.handle, int(tune_class), int(rows_per_lane), int(waves_per_cu)))
+
+    def get_tuning(self, tune_class: int):
+        R, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.sw_context_get_tuning(self.handle, int(tune_class), ctypes.byref(R), ctypes.byref(w)))
+        return R.value, w.value
 
     # -- host-pointer entry points
     def score(self, a, b, scoring=DEFAULT_SCORING, **opts) -> Score:

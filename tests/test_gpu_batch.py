@@ -68,3 +68,85 @@ def test_batch_errors(ctx):
     with pytest.raises(swmi.SwError):
         ctx.batch([(b"ACGT", b"ACGT"), (b"ACXT", b"AC")])
     assert ctx.batch([]) == []
+
+
+def _packed(pairs):
+    import torch
+    a = np.concatenate([p.a for p in pairs])
+    b = np.concatenate([p.b for p in pairs])
+    oa = np.concatenate(([0], np.cumsum([p.a.size for p in pairs]))).astype(np.int64)
+    ob = np.concatenate(([0], np.cumsum([p.b.size for p in pairs]))).astype(np.int64)
+    return torch.from_numpy(a).cuda(), oa, torch.from_numpy(b).cuda(), ob
+
+
+def test_batch_graph_replay(orc):
+    """SW_FLAG_GRAPH: capture once, replay with eager calls in between, new letters in the same buffers."""
+    import torch
+    from paper_1304_5966_amd import swmi
+    stream = torch.cuda.Stream()
+    c = swmi.Context(0, stream=stream)
+    try:
+        first = [synth.config3_pair(i) for i in range(120)]
+        d_a, oa, d_b, ob = _packed(first)
+        exp = [orc.sw_score(p.a.tobytes(), p.b.tobytes()) for p in first]
+        ws = torch.empty(c.batch_workspace_size(oa, ob, graph=True), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        for rep in range(3):
+            _case(f"graph replay {rep}")
+            got = c.batch_dev(d_a, oa, d_b, ob, workspace=ws, graph=True)
+            assert [g.key() for g in got] == exp
+            _case(f"eager between replays {rep}")
+            got = c.batch_dev(d_a, oa, d_b, ob, workspace=ws)
+            assert [g.key() for g in got] == exp
+            torch.cuda.synchronize()
+        # Same lengths, different letters, same buffers: the replay must read the new letters.
+        second = [synth.homologous_pair(900 + k, p.a.size, p.b.size, 0.15) for k, p in enumerate(first)]
+        with torch.cuda.stream(stream):
+            d_a.copy_(torch.from_numpy(np.concatenate([p.a for p in second])))
+            d_b.copy_(torch.from_numpy(np.concatenate([p.b for p in second])))
+        exp2 = [orc.sw_score(p.a.tobytes(), p.b.tobytes()) for p in second]
+        for rep in range(2):
+            _case(f"graph replay on new letters {rep}")
+            got = c.batch_dev(d_a, oa, d_b, ob, workspace=ws, graph=True)
+            assert [g.key() for g in got] == exp2
+        # A different batch shape re-captures.
+        third = first[:50]
+        d_a3, oa3, d_b3, ob3 = _packed(third)
+        ws3 = torch.empty(c.batch_workspace_size(oa3, ob3, graph=True), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        _case("graph re-capture on a new shape")
+        got = c.batch_dev(d_a3, oa3, d_b3, ob3, workspace=ws3, graph=True)
+        assert [g.key() for g in got] == exp[:50]
+    finally:
+        c.close()
+
+
+def test_batch_graph_needs_stream():
+    import torch
+    from paper_1304_5966_amd import swmi
+    c = swmi.Context(0, stream=torch.cuda.default_stream(0))
+    try:
+        pairs = [synth.config3_pair(i) for i in range(4)]
+        d_a, oa, d_b, ob = _packed(pairs)
+        _case("graph on the null stream is refused")
+        with pytest.raises(swmi.SwError):
+            c.batch_dev(d_a, oa, d_b, ob, graph=True)
+    finally:
+        c.close()
+
+
+def test_tuning_is_used(ctx, orc):
+    """A tuned shape per class is taken when options leave the shape at 0; results stay exact."""
+    from paper_1304_5966_amd import swmi
+    pairs = [(p.a.tobytes(), p.b.tobytes()) for p in (synth.config3_pair(i) for i in range(40))]
+    exp = [orc.sw_score(a, b) for a, b in pairs]
+    assert ctx.get_tuning(swmi.TUNE_BATCH) == (0, 0)
+    for R, w in ((4, 12), (8, 2), (0, 0)):
+        ctx.set_tuning(swmi.TUNE_BATCH, R, w)
+        assert ctx.get_tuning(swmi.TUNE_BATCH) == (R, w)
+        _case(f"tuned batch R={R} waves/CU={w}")
+        assert [g.key() for g in ctx.batch(pairs)] == exp
+    with pytest.raises(swmi.SwError):
+        ctx.set_tuning(swmi.TUNE_BATCH, 16, 4)
+    with pytest.raises(swmi.SwError):
+        ctx.set_tuning(7, 8, 4)
