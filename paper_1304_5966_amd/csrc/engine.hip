@@ -96,11 +96,12 @@ __device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need,
     asm volatile("" ::: "memory");
 }
 
-__device__ __forceinline__ uint32_t row_table(int code, int match, int mismatch) {
+// Four score bytes s(a, c) + bias for c = 0..3 (pad row: all -128).
+__device__ __forceinline__ uint32_t row_table(int code, int match, int mismatch, int bias) {
     if (code > 3) return kPadTable;
-    const uint32_t mm = (uint32_t)(uint8_t)(int8_t)(-mismatch) * 0x01010101u;
+    const uint32_t mm = (uint32_t)(uint8_t)(int8_t)(bias - mismatch) * 0x01010101u;
     const int sh = 8 * code;
-    return (mm & ~(0xffu << sh)) | ((uint32_t)(uint8_t)match << sh);
+    return (mm & ~(0xffu << sh)) | ((uint32_t)(uint8_t)(int8_t)(match + bias) << sh);
 }
 
 // H on row 0 (top) or column 0 (left) at distance k >= 1 from the corner; a
@@ -126,6 +127,7 @@ struct WaveState {
 
 struct TickCtx {
     const int2* in;       // LDS: 64 lane-0 inputs {H, F-candidate} of this tick
+    const int2* in_cd;    // the same inputs plus m * ext (column-shifted domain, step m)
     int2* out;            // LDS: 64 lane-63 outputs
     int2* lbuf;           // right-boundary store for the next band (capture)
     int32_t* out_h;       // last-row outputs (reconstruction halves)
@@ -142,22 +144,30 @@ struct TickCtx {
     bool capture;         // store H,E at the band's last column into lbuf
 };
 
-// One tick: 64 steps of the skewed stripe.
-//  TRACK: replay -- no outputs, no maxima; records the first column where a
-//         wanted row reaches its maximum.
-//  SLOW:  per-step predicates -- lanes left of the band's first column hold
-//         their state (tick 0); H,E at the band's last column go to lbuf; the
-//         last matrix row's H and F go to out_h/out_f.
-template <int R, bool LOCAL, bool TRACK, bool SLOW>
+// Tick modes.
+//  kRun:   compute; per-row running maxima.
+//  kTrack: replay -- no outputs, no maxima; records the first column where a
+//          wanted row reaches its (already known) maximum.
+//  kExact: replay -- no outputs; per-row maxima and their first columns.
+constexpr int kRun = 0, kTrack = 1, kExact = 2;
+
+// One tick: 64 steps of the skewed stripe in the plain domain.
+//  SLOW: per-step predicates -- lanes left of the band's first column hold
+//        their state (tick 0); H,E at the band's last column go to lbuf; the
+//        last matrix row's H and F go to out_h/out_f.
+//  CD:   the row tables hold s + ext (the shifted-domain tables); subtract it.
+template <int R, bool LOCAL, int MODE, bool SLOW, bool CD>
 __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, const TickCtx& c,
                                          const bool (&want)[R]) {
+    constexpr bool REPLAY = MODE != kRun;
     const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
     uint32_t lo = src[0], hi = src[1];
     // lane 0's inputs are read one 4-step group ahead (the ring holds 64 + 4 entries)
     const int4* in4 = reinterpret_cast<const int4*>(c.in);
     int4 nx0 = in4[0], nx1 = in4[1];
-    constexpr int kUnroll = (SLOW || TRACK) ? 1 : 2;  // the hot path renames its carried registers
+    const int bias = CD ? c.ext : 0;
+    constexpr int kUnroll = (SLOW || REPLAY) ? 1 : 2;  // the hot path renames its carried registers
 #pragma unroll kUnroll
     for (int g = 0; g < kTick / 4; ++g) {
         const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
@@ -183,12 +193,12 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
             const bool act = SLOW ? (rel >= 0) : true;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const int Hd = diag + sext_byte(sc[k], i);
+                const int Hd = diag + sext_byte(sc[k], i) - bias;
                 const int En = LOCAL ? max(max(s.E[k] - c.ext, s.HA[k]), 0) : max(s.E[k] - c.ext, s.HA[k]);
                 const int Hn = max(max(Hd, En), F);
                 const int HAn = Hn - c.open;
                 if (SLOW) {
-                    if (!TRACK && c.out_k == k && c.lane == c.out_lane && act && rel < c.W) {
+                    if (!REPLAY && c.out_k == k && c.lane == c.out_lane && act && rel < c.W) {
                         c.out_h[c.out_base + rel] = Hn;
                         c.out_f[c.out_base + rel] = F;
                     }
@@ -201,15 +211,20 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
                         s.E[k] = En;
                         s.HA[k] = HAn;
                     }
-                    if (!TRACK && c.capture && rel == c.W - 1 && k < c.M_rows)
+                    if (!REPLAY && c.capture && rel == c.W - 1 && k < c.M_rows)
                         st_shared_i2(c.lbuf + c.row0 + k, make_int2(Hn, En));
                 } else {
                     s.H[k] = Hn;
                     s.E[k] = En;
                     s.HA[k] = HAn;
                 }
-                if (TRACK) {
+                if (MODE == kTrack) {
                     if (act && want[k] && s.pos[k] < 0 && Hn == s.best[k]) s.pos[k] = (int)(c.col0 + m - c.lane);
+                } else if (MODE == kExact) {
+                    if (act && Hn > s.best[k]) {
+                        s.best[k] = Hn;
+                        s.pos[k] = (int)(c.col0 + m - c.lane);
+                    }
                 } else if (SLOW) {
                     if (act) s.best[k] = max(s.best[k], Hn);
                 } else {
@@ -218,9 +233,93 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
             }
             s.hl = s.H[R - 1];
             s.gl = F;
-            if (!TRACK && c.lane == kWave - 1) c.out[m] = make_int2(s.hl, s.gl);
+            if (!REPLAY && c.lane == kWave - 1) c.out[m] = make_int2(s.hl, s.gl);
         }
     }
+}
+
+// One fast tick of the local recurrence in the column-shifted domain: at step
+// m every value of lane l is stored plus z = (m - l) * ext, i.e. plus ext per
+// DP column.  With g = open - ext the recurrence becomes
+//     E~ = max(E~', H~' - g, z)    H~ = max(H~diag + (s + ext), E~, F~)
+//     F~(next row) = max(F~, H~ - g) - ext
+// (the row tables already hold s + ext): E's extension cost and the zero floor
+// cost nothing extra, and a value handed to the next lane keeps its offset
+// because that lane works on the same column one step later.  Lane 63's
+// outputs stay shifted (out[m] carries z = (m - 63) * ext).  Instead of per-row
+// maxima the tick returns the lane's exact maximum H (plain domain).
+template <int R>
+__device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
+    const int ext = c.ext, g = c.open - c.ext;
+    const int off = -(c.lane + 1) * ext;  // the carried state belongs to step -1
+    int HA[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        s.H[k] += off;
+        s.E[k] += off;
+        HA[k] = s.H[k] - g;
+    }
+    s.hup += off;
+    s.hl += off;
+    s.gl += off;
+    int z = -c.lane * ext;
+    int acc = kNeg;  // max over the steps so far of (H - z_step), plus the current z
+    const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
+    uint32_t lo = src[0], hi = src[1];
+    const int4* in4 = reinterpret_cast<const int4*>(c.in_cd);
+    int4 nx0 = in4[0], nx1 = in4[1];
+#pragma unroll 2
+    for (int gi = 0; gi < kTick / 4; ++gi) {
+        const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
+        lo = hi;
+        hi = src[gi + 2];
+        const int2 ins[4] = {make_int2(nx0.x, nx0.y), make_int2(nx0.z, nx0.w), make_int2(nx1.x, nx1.y),
+                             make_int2(nx1.z, nx1.w)};
+        nx0 = in4[2 * gi + 2];
+        nx1 = in4[2 * gi + 3];
+        uint32_t sc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, s.T[k], cw);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = 4 * gi + i;
+            const int upH = dpp_shr1(ins[i].x, s.hl);
+            const int upG = dpp_shr1(ins[i].y, s.gl);
+            int diag = s.hup;
+            s.hup = upH;
+            int F = upG;
+            acc += ext;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int Hd = diag + sext_byte(sc[k], i);
+                const int En = max(max(s.E[k], HA[k]), z);
+                const int Hn = max(max(Hd, En), F);
+                const int HAn = Hn - g;
+                F = max(F, HAn) - ext;
+                diag = s.H[k];
+                s.H[k] = Hn;
+                s.E[k] = En;
+                HA[k] = HAn;
+                acc = max(acc, Hn);
+            }
+            s.hl = s.H[R - 1];
+            s.gl = F;
+            if (c.lane == kWave - 1) c.out[m] = make_int2(s.hl, s.gl);
+            z += ext;
+        }
+    }
+    const int back = (kTick - 1 - c.lane) * ext;  // offset of step 63
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        s.H[k] -= back;
+        s.E[k] -= back;
+        s.HA[k] = s.H[k] - c.open;
+    }
+    s.hup -= back;
+    s.hl -= back;
+    s.gl -= back;
+    return acc - back;
 }
 
 // Does task (band, stripe q) of problem `pr` hold any cell of the kept diagonal band?
@@ -234,10 +333,14 @@ __device__ __forceinline__ bool task_active(const Prob& pr, int64_t band, int64_
     return !(dmax < pr.d_lo || dmin > pr.d_hi);
 }
 
-template <int R, bool LOCAL>
+// CD: fast ticks of the local recurrence run in the column-shifted domain
+// (run_tick_cd); needs match + ext <= 127 so that s + ext fits the score bytes.
+template <int R, bool LOCAL, bool CD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void engine_kernel(
     EngineArgs p) {
+    static_assert(LOCAL || !CD, "the shifted domain is for the local recurrence");
     __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
+    __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
     __shared__ int2 out_buf[kTick];
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
     const int lane = threadIdx.x;
@@ -326,7 +429,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                     e = kNeg;
                 }
             }
-            s.T[k] = row_table(code, p.match, p.mismatch);
+            s.T[k] = row_table(code, p.match, p.mismatch, CD ? p.ext : 0);
             s.H[k] = h;
             s.E[k] = e;
             s.HA[k] = h - p.open;
@@ -368,7 +471,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 wait_at_least(prod_prog, 1, prod_seen);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
             }
-            in_ring[0][lane] = fetch(0, min(kTick, W));
+            const int2 v = fetch(0, min(kTick, W));
+            in_ring[0][lane] = v;
+            if (CD) in_ring_cd[0][lane] = make_int2(v.x + lane * p.ext, v.y + lane * p.ext);
             if (lane == 0) s.hup = h_diag;
         }
         __syncthreads();
@@ -405,6 +510,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             const bool slow = (tau == 0) || has_out ||
                               (capture && kTick * tau - (kTick - 1) <= W - 1 && W - 1 <= kTick * tau + (kTick - 1));
             c.in = in_ring[cur];
+            c.in_cd = in_ring_cd[CD ? cur : 0];
             c.col0 = c0 + (int64_t)kTick * tau;
             c.rel0 = kTick * tau;
 
@@ -427,6 +533,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 }
             }
 
+            const bool cd_tick = CD && !skip && !slow && pr.track;
             if (skip) {
                 pruned += (unsigned long long)kTick * kWave * R;
 #pragma unroll
@@ -441,6 +548,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 s.hl = NEGV;
                 s.gl = NEGV;
                 out_buf[lane] = make_int2(NEGV, NEGV);
+            } else if (cd_tick) {
+                int H0[R], E0[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    H0[k] = s.H[k];
+                    E0[k] = s.E[k];
+                }
+                const int hup0 = s.hup, hl0 = s.hl, gl0 = s.gl;
+                const int tmax = run_tick_cd<R>(s, cols, c);
+                // A lane whose maximum reached max(running best, target) replays the
+                // tick to find its rows' maxima and their first columns.
+                if (__any(tmax >= L)) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        s.H[k] = H0[k];
+                        s.E[k] = E0[k];
+                        s.HA[k] = H0[k] - p.open;
+                    }
+                    s.hup = hup0;
+                    s.hl = hl0;
+                    s.gl = gl0;
+                    bool want[R];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) want[k] = true;
+                    run_tick<R, LOCAL, kExact, false, CD>(s, cols, c, want);
+                    int mx = kNeg;
+#pragma unroll
+                    for (int k = 0; k < R; ++k)
+                        if (k < M_rows) mx = max(mx, s.best[k]);
+                    mx = wave_max(mx);
+                    if (lane == 0 && mx > gb) atomicMax(gbest, mx);
+                }
             } else {
                 int H0[R], E0[R], bstart[R];
 #pragma unroll
@@ -453,8 +592,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 bool want[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k) want[k] = false;
-                if (slow) run_tick<R, LOCAL, false, true>(s, cols, c, want);
-                else run_tick<R, LOCAL, false, false>(s, cols, c, want);
+                if (slow) run_tick<R, LOCAL, kRun, true, CD>(s, cols, c, want);
+                else run_tick<R, LOCAL, kRun, false, CD>(s, cols, c, want);
 
                 if (pr.track) {
                     bool any = false;
@@ -476,8 +615,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                         s.hup = hup0;
                         s.hl = hl0;
                         s.gl = gl0;
-                        if (slow) run_tick<R, LOCAL, true, true>(s, cols, c, want);
-                        else run_tick<R, LOCAL, true, false>(s, cols, c, want);
+                        if (slow) run_tick<R, LOCAL, kTrack, true, CD>(s, cols, c, want);
+                        else run_tick<R, LOCAL, kTrack, false, CD>(s, cols, c, want);
                         int mx = kNeg;
 #pragma unroll
                         for (int k = 0; k < R; ++k)
@@ -492,10 +631,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             __syncthreads();
             {
                 const int rel = kTick * tau - (kTick - 1) + lane;
-                if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, out_buf[lane]);
+                int2 o = out_buf[lane];
+                if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext
+                    o.x -= (lane - (kTick - 1)) * p.ext;
+                    o.y -= (lane - (kTick - 1)) * p.ext;
+                }
+                if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, o);
             }
             publish_count(p.progress + task, min(kTick * tau + 1, W));
             in_ring[cur ^ 1][lane] = nxt;
+            if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + lane * p.ext, nxt.y + lane * p.ext);
             __syncthreads();
         }
 
@@ -668,14 +813,19 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
     return launch_fill_i32((int32_t*)p, 0, (bytes + 3) / 4, st);
 }
 
-hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, int grid, hipStream_t st) {
-    if (local) {
-        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true>), dim3(grid), dim3(kWave), 0, st, args);
-        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true>), dim3(grid), dim3(kWave), 0, st, args);
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, bool cd, int grid, hipStream_t st) {
+    const dim3 g(grid), b(kWave);
+    if (local && cd) {
+        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true, true>), g, b, 0, st, args);
+        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true, true>), g, b, 0, st, args);
+        else return hipErrorInvalidValue;
+    } else if (local) {
+        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true, false>), g, b, 0, st, args);
+        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true, false>), g, b, 0, st, args);
         else return hipErrorInvalidValue;
     } else {
-        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, false>), dim3(grid), dim3(kWave), 0, st, args);
-        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, false>), dim3(grid), dim3(kWave), 0, st, args);
+        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, false, false>), g, b, 0, st, args);
+        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, false, false>), g, b, 0, st, args);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();

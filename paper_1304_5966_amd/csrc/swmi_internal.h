@@ -84,7 +84,9 @@ hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pa
 hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
                               const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad,
                               hipStream_t st);
-hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, int grid, hipStream_t st);
+// cd: run the local recurrence's fast ticks in the column-shifted domain
+// (requires match + gap_extend <= 127).
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, bool cd, int grid, hipStream_t st);
 hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
                          const unsigned long long* pruned, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

@@ -1,9 +1,11 @@
 """Trains the pruning-threshold network on the GPU with the library's own kernels.
 
-    python -m paper_1304_5966_amd.train [--out PATH] [--n-small 2400] [--n-full 48]
+    python -m paper_1304_5966_amd.train [--out PATH] [--n-small 4000] [--n-full 200]
+    python -m paper_1304_5966_amd.train --label-only --dump labels.npz ...   # labelling only
+    python -m paper_1304_5966_amd.train --data a.npz b.npz                   # train on dumps
 
 Training pairs come from the learned-pruning generator with its training seed
-(never the evaluation seed): ``n_small`` pairs of 20-400 kbp per side and
+(never the evaluation seed): ``n_small`` pairs of 50-400 kbp per side and
 ``n_full`` pairs of 1-4 Mbp.  Labels are the exact best scores returned by the
 library's batched score pass; features come from ``sw_features_dev``;
 forward, backward and Adam run as the library's HIP kernels.  Host code only
@@ -127,12 +129,29 @@ def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, seed=0, log=print)
     return mean, inv, d_p.cpu().numpy(), hist
 
 
+def load_dumps(paths):
+    feats, scores = [], []
+    for path in paths:
+        with np.load(path) as d:
+            feats.append(d["feats"])
+            scores.append(d["scores"])
+    return np.concatenate(feats), np.concatenate(scores)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
-    ap.add_argument("--n-small", type=int, default=2400)
-    ap.add_argument("--n-full", type=int, default=48)
+    ap.add_argument("--n-small", type=int, default=4000)
+    ap.add_argument("--small-lo", type=int, default=50_000)
+    ap.add_argument("--small-hi", type=int, default=400_000)
+    ap.add_argument("--n-full", type=int, default=200)
+    ap.add_argument("--full-start", type=int, default=0, help="index of the first full-size pair")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--dump", default=None, help="write features, scores and lengths of the labelled pairs here")
+    ap.add_argument("--label-only", action="store_true", help="label and dump, do not train")
+    ap.add_argument("--data", nargs="*", default=None,
+                    help="train on these dumps instead of labelling (features and exact scores)")
     args = ap.parse_args()
 
     def log(m):
@@ -140,18 +159,33 @@ def main():
 
     ctx = swmi.Context(0)
     t0 = time.time()
-    pairs = [synth.config4_pair(i, synth.SEED_CONFIG4_TRAIN, 20_000, 400_000) for i in range(args.n_small)]
-    pairs += [synth.config4_pair(1_000_000 + i, synth.SEED_CONFIG4_TRAIN) for i in range(args.n_full)]
-    log(f"generated {len(pairs)} training pairs in {time.time() - t0:.1f} s")
-    scores, feats = label_and_featurize(ctx, pairs, log=log)
-    log(f"labels and features in {time.time() - t0:.1f} s")
-    mean, inv, params, hist = train(ctx, feats, scores, epochs=args.epochs, log=log)
+    if args.data:
+        feats, scores = load_dumps(args.data)
+        n_pairs = len(scores)
+        log(f"loaded {n_pairs} labelled pairs")
+    else:
+        pairs = [synth.config4_pair(i, synth.SEED_CONFIG4_TRAIN, args.small_lo, args.small_hi)
+                 for i in range(args.n_small)]
+        pairs += [synth.config4_pair(1_000_000 + i, synth.SEED_CONFIG4_TRAIN)
+                  for i in range(args.full_start, args.full_start + args.n_full)]
+        n_pairs = len(pairs)
+        log(f"generated {n_pairs} training pairs in {time.time() - t0:.1f} s")
+        scores, feats = label_and_featurize(ctx, pairs, log=log)
+        log(f"labels and features in {time.time() - t0:.1f} s")
+        if args.dump:
+            np.savez_compressed(args.dump, feats=feats, scores=scores,
+                                len_a=np.array([p.a.size for p in pairs]),
+                                len_b=np.array([p.b.size for p in pairs]))
+        if args.label_only:
+            return 0
+    mean, inv, params, hist = train(ctx, feats, scores, epochs=args.epochs, lr=args.lr, log=log)
     save_model(args.out, mean, inv, params)
-    meta = {"pairs": len(pairs), "n_small": args.n_small, "n_full": args.n_full, "epochs": args.epochs,
-            "val_mse": hist[-1][1], "seconds": round(time.time() - t0, 1)}
+    meta = {"pairs": n_pairs, "epochs": args.epochs, "lr": args.lr, "val_mse": hist[-1][1],
+            "seconds": round(time.time() - t0, 1)}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     log(json.dumps(meta))
+    return 0
 
 
 if __name__ == "__main__":
