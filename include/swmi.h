@@ -227,11 +227,15 @@ sw_status sw_mlp_standardize_dev(sw_context* ctx, const float* d_feat, int32_t n
 /* Forward pass: h1, h2 [n][128] (post-ReLU, BF16-rounded, stored as float), y [n]. */
 sw_status sw_mlp_forward_dev(sw_context* ctx, const uint16_t* d_x, int32_t n, const uint16_t* d_wbf,
                              const float* d_params, float* d_h1, float* d_h2, float* d_y);
-/* Gradient of mean((y - target)^2) over the n samples into d_grad (same layout
- * as the parameters); d_scratch holds 64 + 257 * n floats.  Fixed summation order. */
+/* Gradient over the n samples into d_grad (same layout as the parameters):
+ * quantile <= 0: of mean((y - target)^2); 0 < quantile < 1: of the mean
+ * pinball loss mean(max(q (target - y), (q - 1) (target - y))), whose
+ * minimiser is the q-quantile of the target (subgradient 0 at y == target);
+ * quantile >= 1: SW_EINVAL.  d_scratch holds 64 + 257 * n floats.  Fixed
+ * summation order. */
 sw_status sw_mlp_backward_dev(sw_context* ctx, const uint16_t* d_x, int32_t n, const uint16_t* d_wbf,
                               const float* d_h1, const float* d_h2, const float* d_y, const float* d_target,
-                              float* d_scratch, float* d_grad);
+                              float quantile, float* d_scratch, float* d_grad);
 /* One Adam step (bias-corrected, step >= 1) on the FP32 parameters; refreshes d_wbf. */
 sw_status sw_mlp_adam_dev(sw_context* ctx, float* d_params, float* d_m, float* d_v, const float* d_grad,
                           int32_t step, float lr, float beta1, float beta2, float eps, uint16_t* d_wbf);

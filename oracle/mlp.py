@@ -9,7 +9,8 @@ include/swmi.h), independently of the GPU kernels:
   positions, diagonal bands, integer log bins).
 * ``forward`` / ``backward``: the 256-128-128-1 ReLU network in float64 on
   BF16-rounded inputs, weights and hidden activations (rounding by torch's CPU
-  bfloat16 conversion); mean-squared error on y.
+  bfloat16 conversion); mean-squared error on y, or with ``quantile`` q in
+  (0, 1) the mean pinball loss max(q r, (q - 1) r), r = t - y.
 * ``forward_exact`` / ``loss_exact``: the same network without activation
   rounding, for central finite differences that check ``backward`` itself.
 """
@@ -122,13 +123,27 @@ def forward(x_bf16: np.ndarray, params: np.ndarray):
     return y, h1, h2
 
 
+def loss_grad(y: np.ndarray, t: np.ndarray, quantile: float = 0.0) -> np.ndarray:
+    """d loss / d y per sample, loss averaged over the samples."""
+    n = y.shape[0]
+    if quantile <= 0:
+        return 2.0 * (y - t) / n
+    return np.where(y > t, 1.0 - quantile, np.where(y < t, -quantile, 0.0)) / n
+
+
+def loss_value(y: np.ndarray, t: np.ndarray, quantile: float = 0.0) -> float:
+    if quantile <= 0:
+        return float(np.mean((y - t) ** 2))
+    r = t - y
+    return float(np.mean(np.maximum(quantile * r, (quantile - 1.0) * r)))
+
+
 def backward(x_bf16: np.ndarray, params: np.ndarray, h1: np.ndarray, h2: np.ndarray, y: np.ndarray,
-             t: np.ndarray) -> np.ndarray:
-    """Gradient of mean((y - t)^2) with respect to the parameters, float64."""
+             t: np.ndarray, quantile: float = 0.0) -> np.ndarray:
+    """Gradient of the loss (see loss_grad) with respect to the parameters, float64."""
     W1, b1, W2, b2, W3, b3 = unpack(params)
     W2, W3 = bf16(W2), bf16(W3)
-    n = x_bf16.shape[0]
-    dy = 2.0 * (y - t) / n
+    dy = loss_grad(y, t, quantile)
     d2 = np.outer(dy, W3) * (h2 > 0)
     d1 = (d2 @ W2.T) * (h1 > 0)
     g = np.zeros(N_PARAMS)
@@ -148,11 +163,10 @@ def forward_exact(x: np.ndarray, params: np.ndarray):
     return h2 @ W3 + b3, h1, h2
 
 
-def backward_exact(x, params, t):
+def backward_exact(x, params, t, quantile: float = 0.0):
     W1, b1, W2, b2, W3, b3 = unpack(params)
     y, h1, h2 = forward_exact(x, params)
-    n = x.shape[0]
-    dy = 2.0 * (y - t) / n
+    dy = loss_grad(y, t, quantile)
     d2 = np.outer(dy, W3) * (h2 > 0)
     d1 = (d2 @ W2.T) * (h1 > 0)
     g = np.zeros(N_PARAMS)
@@ -165,6 +179,6 @@ def backward_exact(x, params, t):
     return g
 
 
-def loss_exact(x, params, t) -> float:
+def loss_exact(x, params, t, quantile: float = 0.0) -> float:
     y, _, _ = forward_exact(x, params)
-    return float(np.mean((y - t) ** 2))
+    return loss_value(y, t, quantile)

@@ -243,15 +243,22 @@ __global__ __launch_bounds__(128) void mlp_fwd_kernel(const uint16_t* __restrict
 }
 
 // Per-sample deltas of the MSE loss mean((y - t)^2): d3 = dL/dy, d2 = dL/dz2, d1 = dL/dz1.
+// dLoss/dy per sample: squared error (quantile <= 0) or pinball loss at the quantile.
+__device__ __forceinline__ float loss_grad(float y, float t, float quantile, int n) {
+    if (quantile <= 0.f) return 2.f * (y - t) / (float)n;
+    const float g = y > t ? 1.f - quantile : (y < t ? -quantile : 0.f);
+    return g / (float)n;
+}
+
 __global__ __launch_bounds__(128) void mlp_delta_kernel(int n, const uint16_t* __restrict__ w,
                                                         const float* __restrict__ h1, const float* __restrict__ h2,
                                                         const float* __restrict__ y, const float* __restrict__ tgt,
-                                                        float* __restrict__ d3, float* __restrict__ d2,
-                                                        float* __restrict__ d1) {
+                                                        float quantile, float* __restrict__ d3,
+                                                        float* __restrict__ d2, float* __restrict__ d1) {
     __shared__ float s2[kHid];
     const int t = threadIdx.x;
     for (int s = blockIdx.x; s < n; s += gridDim.x) {
-        const float dy = 2.f * (y[s] - tgt[s]) / (float)n;
+        const float dy = loss_grad(y[s], tgt[s], quantile, n);
         if (t == 0) d3[s] = dy;
         const float g2 = h2[(int64_t)s * kHid + t] > 0.f ? bf16_to_f32(w[kOffW3 + t]) * dy : 0.f;
         s2[t] = g2;
@@ -425,15 +432,16 @@ extern "C" sw_status sw_mlp_forward_dev(sw_context* ctx, const uint16_t* d_x, in
 
 extern "C" sw_status sw_mlp_backward_dev(sw_context* ctx, const uint16_t* d_x, int32_t n, const uint16_t* d_wbf,
                                          const float* d_h1, const float* d_h2, const float* d_y,
-                                         const float* d_target, float* d_scratch, float* d_grad) {
+                                         const float* d_target, float quantile, float* d_scratch, float* d_grad) {
     if (!ctx || n <= 0 || !d_x || !d_wbf || !d_h1 || !d_h2 || !d_y || !d_target || !d_scratch || !d_grad)
         return fail(SW_EINVAL, "sw_mlp_backward_dev: bad arguments");
+    if (!(quantile < 1.f)) return fail(SW_EINVAL, "sw_mlp_backward_dev: quantile must be < 1");
     HIP_TRY(hipSetDevice(ctx->device));
     float* d3 = d_scratch;
     float* d2 = d3 + align_up((size_t)n, 64);
     float* d1 = d2 + (size_t)n * kHid;
     hipLaunchKernelGGL(mlp_delta_kernel, dim3(std::min(n, 8192)), dim3(128), 0, ctx->stream, n, d_wbf, d_h1, d_h2,
-                       d_y, d_target, d3, d2, d1);
+                       d_y, d_target, quantile, d3, d2, d1);
     hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)((kNParams + 255) / 256)), dim3(256), 0, ctx->stream, n, d_x,
                        d_h1, d_h2, d3, d2, d1, d_grad);
     HIP_TRY(hipGetLastError());

@@ -101,7 +101,7 @@ def _load():
                                   ctypes.c_size_t]
     L.sw_mlp_standardize_dev.argtypes = [vp, vp, i32, vp, vp, vp]
     L.sw_mlp_forward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
-    L.sw_mlp_backward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.sw_mlp_backward_dev.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp]
     L.sw_mlp_adam_dev.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, vp]
     for name in ("sw_context_create", "sw_context_destroy", "sw_context_set_tuning",
@@ -365,13 +365,13 @@ def mlp_forward(ctx, d_x, d_wbf, d_params):
     return y, h1, h2
 
 
-def mlp_backward(ctx, d_x, d_wbf, h1, h2, y, target):
+def mlp_backward(ctx, d_x, d_wbf, h1, h2, y, target, quantile=0.0):
     torch = ctx._torch
     n = d_x.shape[0]
     scratch = torch.empty(64 + 257 * n, dtype=torch.float32, device=d_x.device)
     grad = torch.empty(param_count(), dtype=torch.float32, device=d_x.device)
     _check(lib.sw_mlp_backward_dev(ctx.handle, _ptr(d_x), n, _ptr(d_wbf), _ptr(h1), _ptr(h2), _ptr(y),
-                                   _ptr(target), _ptr(scratch), _ptr(grad)))
+                                   _ptr(target), float(quantile), _ptr(scratch), _ptr(grad)))
     return grad
 
 

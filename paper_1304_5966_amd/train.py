@@ -10,7 +10,9 @@ Training pairs come from the learned-pruning generator with its training seed
 library's batched score pass; features come from ``sw_features_dev``;
 forward, backward and Adam run as the library's HIP kernels.  Host code only
 shuffles, slices mini-batches and computes the standardisation statistics.
-The target is y = ln(1 + S), the loss mean((y_hat - y)^2).
+The target is y = ln(1 + S); the loss is mean((y_hat - y)^2), or with --quantile q the
+mean pinball loss, whose minimiser is the q-quantile of y given the features (a
+conservative prediction keeps T = floor(0.9 * S_hat) below the true score more often).
 """
 from __future__ import annotations
 
@@ -87,7 +89,7 @@ def init_params(rng) -> np.ndarray:
     return p
 
 
-def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, seed=0, log=print):
+def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, quantile=0.0, seed=0, log=print):
     torch = ctx._torch
     dev = torch.device(f"cuda:{ctx.device}")
     y = np.log1p(scores.astype(np.float64)).astype(np.float32)
@@ -118,14 +120,16 @@ def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, seed=0, log=print)
             d_x = torch.from_numpy(x_all[idx]).to(dev)
             d_t = torch.from_numpy(y[idx]).to(dev)
             yh, h1, h2 = swmi.mlp_forward(ctx, d_x, d_w, d_p)
-            g = swmi.mlp_backward(ctx, d_x, d_w, h1, h2, yh, d_t)
+            g = swmi.mlp_backward(ctx, d_x, d_w, h1, h2, yh, d_t, quantile)
             step += 1
             swmi.mlp_adam(ctx, d_p, d_m, d_v, g, step, lr, d_w)
         if ep % 25 == 0 or ep == epochs - 1:
             yv, _, _ = swmi.mlp_forward(ctx, x_val, d_w, d_p)
-            vl = float(np.mean((yv.cpu().numpy() - y[val]) ** 2))
-            hist.append((ep, vl))
-            log(f"epoch {ep} val mse {vl:.4f}")
+            yv = yv.cpu().numpy().astype(np.float64)
+            vl = float(np.mean((yv - y[val]) ** 2))
+            miss = float(np.mean(np.floor(0.9 * np.expm1(yv)) > scores[val]))
+            hist.append((ep, vl, miss))
+            log(f"epoch {ep} val mse {vl:.4f} val miss rate {miss:.3f}")
     return mean, inv, d_p.cpu().numpy(), hist
 
 
@@ -148,6 +152,8 @@ def main():
     ap.add_argument("--full-start", type=int, default=0, help="index of the first full-size pair")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--quantile", type=float, default=0.0,
+                    help="0: squared error on ln(1+S); q in (0,1): pinball loss (predicts the q-quantile)")
     ap.add_argument("--dump", default=None, help="write features, scores and lengths of the labelled pairs here")
     ap.add_argument("--label-only", action="store_true", help="label and dump, do not train")
     ap.add_argument("--data", nargs="*", default=None,
@@ -178,9 +184,11 @@ def main():
                                 len_b=np.array([p.b.size for p in pairs]))
         if args.label_only:
             return 0
-    mean, inv, params, hist = train(ctx, feats, scores, epochs=args.epochs, lr=args.lr, log=log)
+    mean, inv, params, hist = train(ctx, feats, scores, epochs=args.epochs, lr=args.lr, quantile=args.quantile,
+                                    log=log)
     save_model(args.out, mean, inv, params)
-    meta = {"pairs": n_pairs, "epochs": args.epochs, "lr": args.lr, "val_mse": hist[-1][1],
+    meta = {"pairs": n_pairs, "epochs": args.epochs, "lr": args.lr, "quantile": args.quantile,
+            "val_mse": hist[-1][1], "val_miss_rate": hist[-1][2],
             "seconds": round(time.time() - t0, 1)}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)

@@ -71,7 +71,8 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
-def test_forward_backward_against_float64(ctx):
+@pytest.mark.parametrize("quantile", [0.0, 0.1])
+def test_forward_backward_against_float64(ctx, quantile):
     import torch
     from oracle import mlp
     from paper_1304_5966_amd import swmi, train
@@ -88,13 +89,15 @@ def test_forward_backward_against_float64(ctx):
     d_w = torch.from_numpy(train._bf16_bits(params)).cuda()
     _case("mlp forward/backward")
     y, h1, h2 = swmi.mlp_forward(ctx, d_x, d_w, d_p)
-    g = swmi.mlp_backward(ctx, d_x, d_w, h1, h2, y, torch.from_numpy(tgt).cuda())
+    g = swmi.mlp_backward(ctx, d_x, d_w, h1, h2, y, torch.from_numpy(tgt).cuda(), quantile)
     xb = d_x.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     x64 = xb.view(np.float32).astype(np.float64)
     np.testing.assert_array_equal(x64, mlp.bf16(feats))
     ye, h1e, h2e = mlp.forward(x64, params.astype(np.float64))
     assert _rel(y.cpu().numpy(), ye) < 1e-2
-    ge = mlp.backward(x64, params.astype(np.float64), h1e, h2e, ye, tgt.astype(np.float64))
+    # the pinball loss's sign decisions are taken on the GPU's own outputs (both sides decide alike)
+    ysign = y.cpu().numpy().astype(np.float64) if quantile > 0 else ye
+    ge = mlp.backward(x64, params.astype(np.float64), h1e, h2e, ysign, tgt.astype(np.float64), quantile)
     gg = g.cpu().numpy().astype(np.float64)
     for lo, hi in ((mlp.OFF_W1, mlp.OFF_B1), (mlp.OFF_B1, mlp.OFF_W2), (mlp.OFF_W2, mlp.OFF_B2),
                    (mlp.OFF_B2, mlp.OFF_W3), (mlp.OFF_W3, mlp.OFF_B3), (mlp.OFF_B3, mlp.N_PARAMS)):

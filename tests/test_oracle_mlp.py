@@ -5,6 +5,7 @@ a single planted diagonal, bin boundaries) and invariants; the float64
 backward pass is pinned by central finite differences.
 """
 import numpy as np
+import pytest
 
 from oracle import mlp
 from paper_1304_5966_amd import synth
@@ -45,13 +46,16 @@ def test_complement_invariance():
     np.testing.assert_allclose(mlp.features(a, b), mlp.features(a.translate(tr), b.translate(tr)))
 
 
-def test_finite_differences_validate_backward():
+@pytest.mark.parametrize("quantile", [0.0, 0.05, 0.7])
+def test_finite_differences_validate_backward(quantile):
     rng = np.random.default_rng(0)
     n = 6
     x = rng.normal(size=(n, 256))
-    t = rng.normal(size=n)
     p = rng.normal(scale=0.08, size=mlp.N_PARAMS)
-    g = mlp.backward_exact(x, p, t)
+    y, _, _ = mlp.forward_exact(x, p)
+    # targets at least 0.5 away from the outputs keep the pinball loss smooth under the probe
+    t = y + rng.choice([-1.0, 1.0], size=n) * rng.uniform(0.5, 1.5, size=n)
+    g = mlp.backward_exact(x, p, t, quantile)
     idx = np.concatenate([rng.choice(np.arange(mlp.OFF_B1), 12, replace=False),
                           np.arange(mlp.OFF_B1, mlp.OFF_B1 + 3),
                           rng.choice(np.arange(mlp.OFF_W2, mlp.OFF_B2), 12, replace=False),
@@ -61,7 +65,7 @@ def test_finite_differences_validate_backward():
         pp, pm = p.copy(), p.copy()
         pp[q] += eps
         pm[q] -= eps
-        fd = (mlp.loss_exact(x, pp, t) - mlp.loss_exact(x, pm, t)) / (2 * eps)
+        fd = (mlp.loss_exact(x, pp, t, quantile) - mlp.loss_exact(x, pm, t, quantile)) / (2 * eps)
         assert abs(fd - g[q]) <= 1e-5 + 1e-3 * abs(g[q]), q
 
 
@@ -81,3 +85,16 @@ def test_rounded_backward_matches_exact_on_representable_values():
     ge = mlp.backward_exact(x, p, t)
     cos = g @ ge / (np.linalg.norm(g) * np.linalg.norm(ge))
     assert cos > 0.99
+
+
+def test_pinball_loss_pins():
+    """The pinball loss: q * r above the target's side, (1 - q) * |r| below; its minimiser over a
+    constant prediction is the q-quantile of the targets."""
+    t = np.array([0.0, 1.0, 2.0, 3.0, 10.0])
+    assert mlp.loss_value(np.full(5, 2.0), t, 0.25) == pytest.approx(
+        np.mean([0.75 * 2, 0.75 * 1, 0.0, 0.25 * 1, 0.25 * 8]))
+    grid = np.linspace(-1, 11, 1201)
+    best = grid[np.argmin([mlp.loss_value(np.full(5, c), t, 0.2) for c in grid])]
+    assert 0.0 <= best <= 1.0  # any point of [t(1), t(2)] minimises at q = 0.2 with five targets
+    np.testing.assert_array_equal(mlp.loss_grad(np.array([0.0, 1.0, 2.0]), np.array([1.0, 1.0, 1.0]), 0.3),
+                                  np.array([-0.3, 0.0, 0.7]) / 3)
