@@ -181,6 +181,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     const int tR = ctx->tuned_R[cls], tW = ctx->tuned_wpc[cls];
     p.R = rows_per_lane ? rows_per_lane : tR ? tR : 8;
     const int wpc = waves_per_cu ? waves_per_cu : tW ? tW : 8;
+    p.wpc = wpc;
     const int64_t rows_per_stripe = (int64_t)kWave * p.R;
     // Largest-first order keeps the long problems from trailing the launch.
     std::vector<size_t> order(specs.size());
@@ -299,7 +300,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.out_h = out_h;
     a.out_f = out_f;
     const bool cd = plan.local && sc->match + sc->gap_extend <= 127;
-    HIP_TRY(launch_engine(a, plan.R, plan.local, cd, plan.grid, st));
+    HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.pruned, st));
     return SW_OK;
 }

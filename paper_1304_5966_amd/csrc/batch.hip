@@ -133,7 +133,8 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
         uint64_t key = 0x51ed270b7f4a7c15ull;
         for (uint64_t v : {(uint64_t)(uintptr_t)d_a, (uint64_t)(uintptr_t)d_b, (uint64_t)(uintptr_t)ws, (uint64_t)n,
                            (uint64_t)L.plan.n_probs, (uint64_t)L.plan.n_tasks, (uint64_t)L.plan.grid,
-                           (uint64_t)L.plan.R, (uint64_t)L.plan.nslot, (uint64_t)L.plan.slot_stride,
+                           (uint64_t)L.plan.R, (uint64_t)L.plan.wpc, (uint64_t)L.plan.nslot,
+                           (uint64_t)L.plan.slot_stride,
                            (uint64_t)L.plan.total, (uint64_t)L.plan.local, (uint64_t)L.plan.off_slots,
                            (uint64_t)L.plan.off_lbuf, (uint64_t)L.plan.off_recs, (uint64_t)L.plan.off_outs,
                            (uint64_t)L.plan.off_zero, (uint64_t)L.plan.zero_bytes, (uint64_t)L.plan.off_gbest,

@@ -118,11 +118,16 @@ struct WaveState {
     int H[R];      // H of the lane's rows at the last column processed
     int E[R];      // E (clamped at 0 in the local recurrence)
     int HA[R];     // H - open
-    int best[R];   // running maximum of each row
-    int pos[R];    // first column holding best[] (-1 when not tracked)
     uint32_t T[R]; // substitution table of each row
     int hup;       // H received from the row above at the previous step (next diagonal of the first row)
     int hl, gl;    // this lane's last-row H and F-candidate of the previous step (DPP sources)
+};
+
+// Per-row running maxima; kept in LDS between the ticks that need them.
+template <int R>
+struct RowBest {
+    int best[R];   // running maximum of each row
+    int pos[R];    // first column holding best[] (-1 when not tracked)
 };
 
 struct TickCtx {
@@ -157,8 +162,8 @@ constexpr int kRun = 0, kTrack = 1, kExact = 2;
 //        last matrix row's H and F go to out_h/out_f.
 //  CD:   the row tables hold s + ext (the shifted-domain tables); subtract it.
 template <int R, bool LOCAL, int MODE, bool SLOW, bool CD>
-__device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, const TickCtx& c,
-                                         const bool (&want)[R]) {
+__device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const uint8_t* first,
+                                         const TickCtx& c, const bool (&want)[R]) {
     constexpr bool REPLAY = MODE != kRun;
     const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
@@ -219,16 +224,16 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, const uint8_t* first, 
                     s.HA[k] = HAn;
                 }
                 if (MODE == kTrack) {
-                    if (act && want[k] && s.pos[k] < 0 && Hn == s.best[k]) s.pos[k] = (int)(c.col0 + m - c.lane);
+                    if (act && want[k] && rb.pos[k] < 0 && Hn == rb.best[k]) rb.pos[k] = (int)(c.col0 + m - c.lane);
                 } else if (MODE == kExact) {
-                    if (act && Hn > s.best[k]) {
-                        s.best[k] = Hn;
-                        s.pos[k] = (int)(c.col0 + m - c.lane);
+                    if (act && Hn > rb.best[k]) {
+                        rb.best[k] = Hn;
+                        rb.pos[k] = (int)(c.col0 + m - c.lane);
                     }
                 } else if (SLOW) {
-                    if (act) s.best[k] = max(s.best[k], Hn);
+                    if (act) rb.best[k] = max(rb.best[k], Hn);
                 } else {
-                    s.best[k] = max(s.best[k], Hn);
+                    rb.best[k] = max(rb.best[k], Hn);
                 }
             }
             s.hl = s.H[R - 1];
@@ -335,12 +340,17 @@ __device__ __forceinline__ bool task_active(const Prob& pr, int64_t band, int64_
 
 // CD: fast ticks of the local recurrence run in the column-shifted domain
 // (run_tick_cd); needs match + ext <= 127 so that s + ext fits the score bytes.
-template <int R, bool LOCAL, bool CD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void engine_kernel(
-    EngineArgs p) {
+// OCC: resident waves per SIMD the register allocation is sized for
+// (512 / OCC VGPRs per lane).
+template <int R, bool LOCAL, bool CD, int OCC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void engine_kernel(EngineArgs p) {
     static_assert(LOCAL || !CD, "the shifted domain is for the local recurrence");
     __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
     __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
+    // Row maxima and the pre-tick snapshot live in LDS (one column per lane) so
+    // that the hot loop's registers hold only the recurrence.
+    __shared__ int lds_best[R][kWave], lds_pos[R][kWave];
+    __shared__ int lds_snap[2 * R + 3][kWave];
     __shared__ int2 out_buf[kTick];
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
     const int lane = threadIdx.x;
@@ -433,8 +443,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             s.H[k] = h;
             s.E[k] = e;
             s.HA[k] = h - p.open;
-            s.best[k] = LOCAL ? 0 : kNeg;
-            s.pos[k] = -1;
+            lds_best[k][lane] = LOCAL ? 0 : kNeg;
+            lds_pos[k][lane] = -1;
         }
         s.hup = 0;
         s.hl = s.H[R - 1];
@@ -498,14 +508,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             c.out_k = (int)((pr.M - 1 - R0) % R);
         }
         unsigned long long pruned = 0;
+        // The producer's column count and the running best are read one tick
+        // ahead and consumed a tick later, so no tick starts with a round trip
+        // to memory.  Both only grow: a value one tick old is a valid lower bound.
+        const bool polls = q > 0 && prod_active;
+        int32_t prod_pf = 0;
+        int gb_pf = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         for (int tau = 0; tau < n_ticks; ++tau) {
             const int cur = tau & 1;
+            prod_seen = max(prod_seen, prod_pf);
             int2 nxt = make_int2(NEGV, NEGV);
             if (tau + 1 < n_ticks) nxt = fetch(kTick * (tau + 1), min(kTick * (tau + 2), W));
+            if (polls && tau + 2 < n_ticks) prod_pf = load_count(prod_prog);
             const uint8_t* cols = bcodes + c0 + (int64_t)kTick * tau - lane;
 
-            const int gb = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int gb = gb_pf;
+            gb_pf = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int L = max(gb, pr.target);
             const bool slow = (tau == 0) || has_out ||
                               (capture && kTick * tau - (kTick - 1) <= W - 1 && W - 1 <= kTick * tau + (kTick - 1));
@@ -533,6 +552,51 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 }
             }
 
+            auto load_rb = [&](RowBest<R>& rb) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    rb.best[k] = lds_best[k][lane];
+                    rb.pos[k] = lds_pos[k][lane];
+                }
+            };
+            auto store_rb = [&](const RowBest<R>& rb) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    lds_best[k][lane] = rb.best[k];
+                    lds_pos[k][lane] = rb.pos[k];
+                }
+            };
+            auto snapshot = [&]() {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    lds_snap[k][lane] = s.H[k];
+                    lds_snap[R + k][lane] = s.E[k];
+                }
+                lds_snap[2 * R][lane] = s.hup;
+                lds_snap[2 * R + 1][lane] = s.hl;
+                lds_snap[2 * R + 2][lane] = s.gl;
+            };
+            auto restore = [&]() {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    s.H[k] = lds_snap[k][lane];
+                    s.E[k] = lds_snap[R + k][lane];
+                    s.HA[k] = s.H[k] - p.open;
+                }
+                s.hup = lds_snap[2 * R][lane];
+                s.hl = lds_snap[2 * R + 1][lane];
+                s.gl = lds_snap[2 * R + 2][lane];
+            };
+            // Best of the rows that may hold the answer, into the problem's running best.
+            auto publish_best = [&](const RowBest<R>& rb, const bool (&want)[R]) {
+                int mx = kNeg;
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (want[k] && k < M_rows) mx = max(mx, rb.best[k]);
+                mx = wave_max(mx);
+                if (lane == 0 && mx > gb) atomicMax(gbest, mx);
+            };
+
             const bool cd_tick = CD && !skip && !slow && pr.track;
             if (skip) {
                 pruned += (unsigned long long)kTick * kWave * R;
@@ -549,82 +613,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
                 s.gl = NEGV;
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
-                int H0[R], E0[R];
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    H0[k] = s.H[k];
-                    E0[k] = s.E[k];
-                }
-                const int hup0 = s.hup, hl0 = s.hl, gl0 = s.gl;
+                snapshot();
                 const int tmax = run_tick_cd<R>(s, cols, c);
                 // A lane whose maximum reached max(running best, target) replays the
                 // tick to find its rows' maxima and their first columns.
                 if (__any(tmax >= L)) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        s.H[k] = H0[k];
-                        s.E[k] = E0[k];
-                        s.HA[k] = H0[k] - p.open;
-                    }
-                    s.hup = hup0;
-                    s.hl = hl0;
-                    s.gl = gl0;
+                    restore();
                     bool want[R];
 #pragma unroll
                     for (int k = 0; k < R; ++k) want[k] = true;
-                    run_tick<R, LOCAL, kExact, false, CD>(s, cols, c, want);
-                    int mx = kNeg;
-#pragma unroll
-                    for (int k = 0; k < R; ++k)
-                        if (k < M_rows) mx = max(mx, s.best[k]);
-                    mx = wave_max(mx);
-                    if (lane == 0 && mx > gb) atomicMax(gbest, mx);
+                    RowBest<R> rb;
+                    load_rb(rb);
+                    run_tick<R, LOCAL, kExact, false, CD>(s, rb, cols, c, want);
+                    store_rb(rb);
+                    publish_best(rb, want);
                 }
             } else {
-                int H0[R], E0[R], bstart[R];
+                RowBest<R> rb;
+                load_rb(rb);
+                int bstart[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    H0[k] = s.H[k];
-                    E0[k] = s.E[k];
-                    bstart[k] = s.best[k];
-                }
-                const int hup0 = s.hup, hl0 = s.hl, gl0 = s.gl;
+                for (int k = 0; k < R; ++k) bstart[k] = rb.best[k];
+                if (pr.track) snapshot();
                 bool want[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k) want[k] = false;
-                if (slow) run_tick<R, LOCAL, kRun, true, CD>(s, cols, c, want);
-                else run_tick<R, LOCAL, kRun, false, CD>(s, cols, c, want);
+                if (slow) run_tick<R, LOCAL, kRun, true, CD>(s, rb, cols, c, want);
+                else run_tick<R, LOCAL, kRun, false, CD>(s, rb, cols, c, want);
 
                 if (pr.track) {
                     bool any = false;
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
-                        const bool inc = s.best[k] > bstart[k];
-                        want[k] = inc && s.best[k] >= L;
-                        if (inc) s.pos[k] = -1;
+                        const bool inc = rb.best[k] > bstart[k];
+                        want[k] = inc && rb.best[k] >= L;
+                        if (inc) rb.pos[k] = -1;
                         any = any || want[k];
                     }
                     if (__any(any)) {
                         // Replay from the snapshot; the replay ends in the same state.
-#pragma unroll
-                        for (int k = 0; k < R; ++k) {
-                            s.H[k] = H0[k];
-                            s.E[k] = E0[k];
-                            s.HA[k] = H0[k] - p.open;
-                        }
-                        s.hup = hup0;
-                        s.hl = hl0;
-                        s.gl = gl0;
-                        if (slow) run_tick<R, LOCAL, kTrack, true, CD>(s, cols, c, want);
-                        else run_tick<R, LOCAL, kTrack, false, CD>(s, cols, c, want);
-                        int mx = kNeg;
-#pragma unroll
-                        for (int k = 0; k < R; ++k)
-                            if (want[k]) mx = max(mx, s.best[k]);
-                        mx = wave_max(mx);
-                        if (lane == 0 && mx > gb) atomicMax(gbest, mx);
+                        restore();
+                        if (slow) run_tick<R, LOCAL, kTrack, true, CD>(s, rb, cols, c, want);
+                        else run_tick<R, LOCAL, kTrack, false, CD>(s, rb, cols, c, want);
+                        publish_best(rb, want);
                     }
                 }
+                store_rb(rb);
             }
 
             // Hand the 64 bottom-row columns of this tick to the stripe below.
@@ -649,10 +683,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
             int bv = kNeg, bk = 0, bp = -1;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (k < M_rows && s.best[k] > bv) {
-                    bv = s.best[k];
+                const int b = lds_best[k][lane];
+                if (k < M_rows && b > bv) {
+                    bv = b;
                     bk = k;
-                    bp = s.pos[k];
+                    bp = lds_pos[k][lane];
                 }
             }
             const int vmax = wave_max(bv);
@@ -813,21 +848,22 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
     return launch_fill_i32((int32_t*)p, 0, (bytes + 3) / 4, st);
 }
 
-hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, bool cd, int grid, hipStream_t st) {
-    const dim3 g(grid), b(kWave);
-    if (local && cd) {
-        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true, true>), g, b, 0, st, args);
-        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true, true>), g, b, 0, st, args);
-        else return hipErrorInvalidValue;
-    } else if (local) {
-        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, true, false>), g, b, 0, st, args);
-        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, true, false>), g, b, 0, st, args);
-        else return hipErrorInvalidValue;
-    } else {
-        if (rows_per_lane == 4) hipLaunchKernelGGL((engine_kernel<4, false, false>), g, b, 0, st, args);
-        else if (rows_per_lane == 8) hipLaunchKernelGGL((engine_kernel<8, false, false>), g, b, 0, st, args);
-        else return hipErrorInvalidValue;
-    }
+template <bool LOCAL, bool CD>
+static void launch_variant(const EngineArgs& args, int R, int occ, dim3 g, hipStream_t st) {
+    const dim3 b(kWave);
+    if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4>), g, b, 0, st, args);
+    else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2>), g, b, 0, st, args);
+    else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3>), g, b, 0, st, args);
+}
+
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
+                         hipStream_t st) {
+    if (rows_per_lane != 4 && rows_per_lane != 8) return hipErrorInvalidValue;
+    const int occ = (waves_per_cu + 3) / 4;  // waves per SIMD (4 SIMDs per CU)
+    const dim3 g(grid);
+    if (local && cd) launch_variant<true, true>(args, rows_per_lane, occ, g, st);
+    else if (local) launch_variant<true, false>(args, rows_per_lane, occ, g, st);
+    else launch_variant<false, false>(args, rows_per_lane, occ, g, st);
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ struct ProbSpec {
 // Decomposition and workspace layout of one engine launch.
 struct EnginePlan {
     int R = 8;
+    int wpc = 8;  // resident stripe waves per CU the launch is sized for
     int grid = 1;
     bool local = true;
     int64_t n_probs = 0, n_tasks = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;

@@ -86,7 +86,10 @@ hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const 
                               hipStream_t st);
 // cd: run the local recurrence's fast ticks in the column-shifted domain
 // (requires match + gap_extend <= 127).
-hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, bool local, bool cd, int grid, hipStream_t st);
+// waves_per_cu picks the register budget: rows_per_lane 8 runs 2 waves per SIMD
+// (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
+hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
+                         hipStream_t st);
 hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
                          const unsigned long long* pruned, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

@@ -32,30 +32,30 @@ def _case(msg):
 SIZES = [1, 2, 3, 63, 64, 65, 255, 256, 257, 511, 512, 513, 700, 1031]
 
 
-@pytest.mark.parametrize("rows_per_lane", [4, 8])
-def test_random_shapes(ctx, orc, rows_per_lane):
-    rng = np.random.default_rng(7 + rows_per_lane)
+@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 12), (4, 16)])
+def test_random_shapes(ctx, orc, rows_per_lane, waves_per_cu):
+    rng = np.random.default_rng(7 + rows_per_lane + waves_per_cu)
     for t in range(24):
         la, lb = int(rng.choice(SIZES)), int(rng.choice(SIZES))
         p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.15) if t % 2 else \
             synth.random_pair(int(rng.integers(1 << 30)), la, lb)
         a, b = p.a.tobytes(), p.b.tobytes()
-        _case(f"random_shapes R={rows_per_lane} {la}x{lb} t={t}")
+        _case(f"random_shapes R={rows_per_lane} waves/CU={waves_per_cu} {la}x{lb} t={t}")
         exp = orc.sw_score(a, b)
-        got = ctx.score(a, b, rows_per_lane=rows_per_lane)
+        got = ctx.score(a, b, rows_per_lane=rows_per_lane, waves_per_cu=waves_per_cu)
         assert got.key() == exp, (la, lb, t)
 
 
 @pytest.mark.parametrize("prune", [0, 1])
-@pytest.mark.parametrize("rows_per_lane", [4, 8])
-def test_homologous_multi_stripe(ctx, orc, prune, rows_per_lane):
+@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 10)])
+def test_homologous_multi_stripe(ctx, orc, prune, rows_per_lane, waves_per_cu):
     rng = np.random.default_rng(100 + prune + rows_per_lane)
     for la, lb in [(3000, 2900), (2100, 3300), (4100, 700), (900, 5000)]:
         p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.08)
         a, b = p.a.tobytes(), p.b.tobytes()
-        _case(f"homologous R={rows_per_lane} prune={prune} {la}x{lb}")
+        _case(f"homologous R={rows_per_lane} waves/CU={waves_per_cu} prune={prune} {la}x{lb}")
         exp = orc.sw_score(a, b)
-        got = ctx.score(a, b, prune=prune, rows_per_lane=rows_per_lane)
+        got = ctx.score(a, b, prune=prune, rows_per_lane=rows_per_lane, waves_per_cu=waves_per_cu)
         assert got.key() == exp
 
 
@@ -117,8 +117,11 @@ def test_empty_and_errors(ctx):
 
 
 def test_other_scorings(ctx, orc):
+    """Includes scorings at and beyond match + gap_extend = 127, where the local pass leaves the
+    column-shifted domain for the plain one."""
     rng = np.random.default_rng(11)
-    for sc in [(2, 1, 3, 1), (1, 1, 2, 2), (3, 2, 7, 1), (5, 4, 12, 3)]:
+    for sc in [(2, 1, 3, 1), (1, 1, 2, 2), (3, 2, 7, 1), (5, 4, 12, 3), (100, 120, 30, 27), (100, 3, 30, 28),
+               (1, 3, 150, 130), (1, 127, 2, 1)]:
         p = synth.homologous_pair(int(rng.integers(1 << 30)), 1200, 1100, 0.2)
         a, b = p.a.tobytes(), p.b.tobytes()
         _case(f"scoring {sc}")
