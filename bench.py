@@ -123,10 +123,10 @@ def main():
     tune = None
     if not (args.no_tune or args.rows_per_lane or args.waves_per_cu):
         from paper_1304_5966_amd import autotune
-        log("autotuning the engine shape on the leading 2 Mbp x 2 Mbp of the pair")
-        tune = {"sample": "leading 2 Mbp x 2 Mbp of the pair", "candidates": []}
-        tune["chosen"] = autotune.tune_score(ctx, d_a, d_b, crop=2_000_000, use_cache=False, log=log,
-                                             table=tune["candidates"])
+        log("autotuning the engine shape on the pair itself (one pass per candidate)")
+        tune = {"sample": "the whole pair, one pass per candidate", "candidates": []}
+        tune["chosen"] = autotune.tune_score(ctx, d_a, d_b, use_cache=False, log=log, table=tune["candidates"],
+                                             candidates=[(8, 6), (8, 8), (8, 10), (8, 12), (4, 12)])
     ws = ctx.workspace(ctx.workspace_size(M, N, **opts))
     stream = torch.cuda.current_stream(dev)
 

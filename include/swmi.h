@@ -200,7 +200,12 @@ sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* 
 /* ---- Learned pruning threshold (not in the paper; see the pruning rule of
  * Section 2, which it feeds).  A 256-128-128-1 ReLU network with BF16
  * weights and inputs and FP32 accumulation predicts y = ln(1 + S) from pair
- * features; the threshold is T = floor(0.9 * (exp(y) - 1)).  Parameters are one
+ * features; the threshold is T = floor(0.9 * (exp(y) - 1)), or none (T = 0)
+ * when T < 0.01 |A||B| / (|A| + |B|): such a threshold could skip under 2 % of
+ * the cells.  A pass that finds a best below T (a miss) reports the largest H
+ * it computed, S' <= S, and reruns with threshold S' (exact; it cannot miss);
+ * sw_score_result.fallback flags the rerun and cells_computed counts both
+ * passes.  Parameters are one
  * FP32 vector of sw_mlp_param_count() values: W1[256][128], b1[128],
  * W2[128][128], b2[128], W3[128], b3 (row-major, input index first); the BF16
  * copy (d_wbf) holds the same values rounded to nearest even.  All _dev calls

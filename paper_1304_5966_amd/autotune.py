@@ -98,18 +98,18 @@ def _time(fn, reps, warm=True):
     return best
 
 
-def tune_score(ctx, d_a, d_b, crop: int = 2_000_000, reps: int = 1, use_cache: bool = True, log=None,
-               table=None) -> dict:
-    """Best shape for one pair, timed on the leading crop x crop of the pair.
+def tune_score(ctx, d_a, d_b, crop: int | None = None, reps: int = 1, use_cache: bool = True, log=None,
+               table=None, candidates=None) -> dict:
+    """Best shape for one pair, timed on the pair (or its leading crop x crop).
 
     ``table``, if a list, receives one dict per candidate (shape, seconds, GCUPS)."""
     la, lb = int(d_a.numel()), int(d_b.numel())
     cls = workload_class(float(la) * lb, 1)
     if use_cache and (hit := cached(ctx, cls)):
         return _install(ctx, cls, hit)
-    a, b = d_a[:min(la, crop)], d_b[:min(lb, crop)]
+    a, b = (d_a, d_b) if crop is None else (d_a[:min(la, crop)], d_b[:min(lb, crop)])
     rows = []
-    for R, w in CANDIDATES:
+    for R, w in candidates or CANDIDATES:
         opts = dict(rows_per_lane=R, waves_per_cu=w)
         ws = ctx.workspace(ctx.workspace_size(a.numel(), b.numel(), **opts))
         t = _time(lambda: ctx.score_dev(a, b, workspace=ws, **opts), reps, warm=a.numel() * b.numel() < 1e11)

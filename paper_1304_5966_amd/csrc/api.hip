@@ -196,8 +196,11 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
         maxN = std::max(maxN, s.N);
     }
     // Band width: keep the slots (one per resident wave) within a fixed budget.
+    // Wide bands keep the stripe pipeline full: consecutive stripes run about
+    // three ticks apart, so a band of T ticks keeps all waves busy only while
+    // grid * 3 <= T.  32 GiB (of 288 GB HBM) gives 2 Mi columns at 2048 waves.
     const int64_t grid_est = std::max<int64_t>(1, std::min<int64_t>(max_grid, stripes * ((maxN + 63) / 64)));
-    const size_t slot_budget = (size_t)8 << 30;
+    const size_t slot_budget = (size_t)32 << 30;
     int64_t Wg = (int64_t)(slot_budget / ((size_t)(grid_est + 1) * sizeof(int2))) - (kSlotPad + 2 * kTick);
     Wg = std::max<int64_t>(kTick, Wg / kTick * kTick);
     if (band_width) Wg = band_width;
@@ -301,7 +304,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.out_f = out_f;
     const bool cd = plan.local && sc->match + sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
-    HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.pruned, st));
+    HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.gbest, a.pruned, st));
     return SW_OK;
 }
 
@@ -384,7 +387,10 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
 
 // LEARNED mode: T from the model (or the caller), one pass that skips tiles below
 // max(running best, T); if the best found is below T the result is not known to
-// be optimal and the pass reruns with the running best alone (exact).
+// be optimal and the pass reruns.  The missed pass still reports the largest H it
+// computed, a lower bound S' <= S (pruned borders are lower bounds and the
+// recurrence is monotone), so the rerun takes S' as its threshold: exact, and it
+// cannot miss.  With S' = 0 the rerun uses the running best alone.
 sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
                           const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
                           sw_score_result* out) {
@@ -403,10 +409,14 @@ sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const 
     out->threshold = ol.threshold;
     if (out->score < ol.threshold) {
         const int64_t first = out->cells_computed;
+        const int32_t seen = out->score;
         sw_options ob = ol;
-        ob.prune_mode = SW_PRUNE_BEST;
-        ob.threshold = 0;
+        ob.model = nullptr;
+        ob.prune_mode = seen > 0 ? SW_PRUNE_LEARNED : SW_PRUNE_BEST;
+        ob.threshold = seen > 0 ? seen : 0;
         if ((st = run_score_once(ctx, d_a, M, d_b, N, sc, &ob, ws, ws_bytes, out)) != SW_OK) return st;
+        if (out->score < ob.threshold)
+            return fail(SW_EINTERNAL, "learned fallback: rerun below the seen lower bound %d", seen);
         out->threshold = ol.threshold;
         out->fallback = 1;
         out->cells_computed += first;

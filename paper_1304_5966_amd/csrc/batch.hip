@@ -233,8 +233,9 @@ extern "C" size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a
 }
 
 // Batched pass; in LEARNED mode with a model: thresholds first, then one pass,
-// then the pairs whose best fell below their threshold again with the running
-// best alone (exact), flagged as fallbacks.
+// then the pairs whose best fell below their threshold again, each with the
+// largest H its missed pass computed as threshold (a lower bound of its optimum:
+// exact, cannot miss), flagged as fallbacks.
 static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, const std::vector<int64_t>& as,
                            const std::vector<int64_t>& al, const std::vector<int64_t>& bs,
                            const std::vector<int64_t>& bl, const sw_scoring* sc, const sw_options* o, void* ws,
@@ -278,7 +279,7 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
     if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out, graph)) != SW_OK) return st;
     if (!o || o->prune_mode != SW_PRUNE_LEARNED) return SW_OK;
     std::vector<int64_t> as2, al2, bs2, bl2;
-    std::vector<int32_t> idx;
+    std::vector<int32_t> idx, T2;
     for (int32_t p = 0; p < n; ++p) {
         const int32_t t = T.empty() ? o->threshold : T[(size_t)p];
         out[p].threshold = t;
@@ -288,19 +289,23 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
             al2.push_back(al[(size_t)p]);
             bs2.push_back(bs[(size_t)p]);
             bl2.push_back(bl[(size_t)p]);
+            T2.push_back(out[p].score);  // largest H seen by the missed pass
         }
     }
     if (idx.empty()) return SW_OK;
     sw_options ob2 = *o;
-    ob2.prune_mode = SW_PRUNE_BEST;
+    ob2.model = nullptr;
+    ob2.prune_mode = SW_PRUNE_LEARNED;
     ob2.threshold = 0;
     BatchLayout L2;
-    if ((st = make_layout(ctx, as2, al2, bs2, bl2, sc, &ob2, nullptr, L2)) != SW_OK) return st;
+    if ((st = make_layout(ctx, as2, al2, bs2, bl2, sc, &ob2, &T2, L2)) != SW_OK) return st;
     if (L2.total > ws_bytes) return fail(SW_ENOMEM, "batch fallback: workspace too small");
     std::vector<sw_score_result> r2(idx.size());
     if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data(), false)) != SW_OK)
         return st;
     for (size_t k = 0; k < idx.size(); ++k) {
+        if (r2[k].score < T2[k])
+            return fail(SW_EINTERNAL, "learned fallback: pair %d below the seen lower bound", idx[k]);
         sw_score_result& r = out[idx[k]];
         const int64_t first = r.cells_computed;
         const int32_t t = r.threshold;

@@ -615,6 +615,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             } else if (cd_tick) {
                 snapshot();
                 const int tmax = run_tick_cd<R>(s, cols, c);
+                if (pr.target > 0) {
+                    // Under an external target, ticks below it are not replayed; keep the
+                    // largest H seen in the running best (a valid lower bound of the optimum)
+                    // so that a missed target still reports it.
+                    const int wm = wave_max(tmax);
+                    if (lane == 0 && wm > gb) atomicMax(gbest, wm);
+                }
                 // A lane whose maximum reached max(running best, target) replays the
                 // tick to find its rows' maxima and their first columns.
                 if (__any(tmax >= L)) {
@@ -759,7 +766,8 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t words) {
 // Per problem: best task record (highest score, then smallest row, then smallest column).
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__ recs, const Prob* __restrict__ probs,
                                                      int64_t n_probs, ScoreOut* out,
-                                                     const unsigned long long* __restrict__ pruned) {
+                                                     const unsigned long long* __restrict__ pruned,
+                                                     const int32_t* __restrict__ gbest) {
     __shared__ int32_t s_v[256];
     __shared__ int64_t s_r[256];
     __shared__ int64_t s_c[256];
@@ -799,7 +807,13 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
             o.pruned_cells = pruned ? pruned[pi] : 0;
             o.status = 0;
             const bool local = pr.top_kind == BORDER_ZERO;
-            if (local && s_v[0] <= 0) {
+            if (local && s_v[0] < pr.target) {
+                // Below the target nothing was tracked: report the largest H seen
+                // (a lower bound of the optimum), without an endpoint.
+                o.score = max(max(s_v[0], gbest[pi]), 0);
+                o.end_a = -1;
+                o.end_b = -1;
+            } else if (local && s_v[0] <= 0) {
                 o.score = 0;
                 o.end_a = -1;
                 o.end_b = -1;
@@ -867,10 +881,10 @@ hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_pe
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out, const int32_t* gbest,
                          const unsigned long long* pruned, hipStream_t st) {
     const int blocks = (int)min((int64_t)4096, max((int64_t)1, n_probs));
-    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, out, pruned);
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, out, pruned, gbest);
     return hipGetLastError();
 }
 

@@ -565,7 +565,12 @@ sw_status predict_thresholds(sw_context* ctx, const sw_model* m, const uint8_t* 
     for (int32_t k = 0; k < n; ++k) {
         const double sh = std::exp((double)y[(size_t)k]) - 1.0;
         const double t = std::floor(0.9 * sh);
-        T[(size_t)k] = t < 0 ? 0 : (t > 1.0e9 ? 1000000000 : (int32_t)t);
+        // A threshold below t_min = 0.01 * |A||B| / (|A| + |B|) can only skip the
+        // strips of that width along the last rows and columns, under 2 % of the
+        // cells: not worth the risk of a rerun, so none is set.
+        const double la = (double)(offs_a[k + 1] - offs_a[k]), lb = (double)(offs_b[k + 1] - offs_b[k]);
+        const double tmin = la + lb > 0 ? 0.01 * la * lb / (la + lb) : 0.0;
+        T[(size_t)k] = (t < 1.0 || t < tmin) ? 0 : (t > 1.0e9 ? 1000000000 : (int32_t)t);
     }
     return SW_OK;
 }

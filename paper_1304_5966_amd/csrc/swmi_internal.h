@@ -90,7 +90,7 @@ hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const 
 // (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st);
-hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out,
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out, const int32_t* gbest,
                          const unsigned long long* pruned, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t st);

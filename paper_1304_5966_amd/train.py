@@ -89,13 +89,23 @@ def init_params(rng) -> np.ndarray:
     return p
 
 
+def thresholds(y_hat: np.ndarray, feats: np.ndarray) -> np.ndarray:
+    """The library's threshold rule on predictions (lengths from the two length features)."""
+    la = np.exp(feats[:, 254].astype(np.float64) * np.log(4.0e6))
+    lb = np.exp(feats[:, 255].astype(np.float64) * np.log(4.0e6))
+    t = np.floor(0.9 * np.expm1(y_hat))
+    tmin = 0.01 * la * lb / (la + lb)
+    return np.where((t < 1) | (t < tmin), 0, t)
+
+
 def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, quantile=0.0, seed=0, log=print):
     torch = ctx._torch
     dev = torch.device(f"cuda:{ctx.device}")
     y = np.log1p(scores.astype(np.float64)).astype(np.float32)
     mean = feats.mean(0).astype(np.float32)
-    std = feats.std(0)
-    inv = np.where(std > 1e-6, 1.0 / np.maximum(std, 1e-6), 0.0).astype(np.float32)
+    # Spread floored at 1: the high histogram bins are populated only by long homologous
+    # pairs, and dividing by their tiny spread over all pairs blows those inputs up.
+    inv = (1.0 / np.maximum(feats.std(0), 1.0)).astype(np.float32)
     rng = np.random.default_rng(seed)
     n = len(y)
     perm = rng.permutation(n)
@@ -127,7 +137,7 @@ def train(ctx, feats, scores, epochs=300, batch=256, lr=2e-3, quantile=0.0, seed
             yv, _, _ = swmi.mlp_forward(ctx, x_val, d_w, d_p)
             yv = yv.cpu().numpy().astype(np.float64)
             vl = float(np.mean((yv - y[val]) ** 2))
-            miss = float(np.mean(np.floor(0.9 * np.expm1(yv)) > scores[val]))
+            miss = float(np.mean(thresholds(yv, feats[val]) > scores[val]))
             hist.append((ep, vl, miss))
             log(f"epoch {ep} val mse {vl:.4f} val miss rate {miss:.3f}")
     return mean, inv, d_p.cpu().numpy(), hist
@@ -152,7 +162,7 @@ def main():
     ap.add_argument("--full-start", type=int, default=0, help="index of the first full-size pair")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--quantile", type=float, default=0.0,
+    ap.add_argument("--quantile", type=float, default=0.1,
                     help="0: squared error on ln(1+S); q in (0,1): pinball loss (predicts the q-quantile)")
     ap.add_argument("--dump", default=None, help="write features, scores and lengths of the labelled pairs here")
     ap.add_argument("--label-only", action="store_true", help="label and dump, do not train")
