@@ -28,11 +28,12 @@
 //    then stripe).  A task only waits on older tasks: the stripe above in the
 //    same band (its bottom row streamed through a global slot with a published
 //    column count), the same stripe in the previous band (its right boundary
-//    H,E per row) and the task that last read the slot being reused.  The
-//    oldest unfinished task never waits: no deadlock, no residency assumption.
+//    H,E per row) and the two tasks that last wrote and read the slot being
+//    reused.  The oldest unfinished task never waits: no deadlock, no
+//    residency assumption.
 //  * Every 64 steps (a tick) the wave exchanges 64 boundary columns: the next
 //    tick's inputs are prefetched, lane 63's outputs go to the task's slot and
-//    the column count is published with release semantics.
+//    the column count is published after the outputs are stored.
 //  * Tile skipping (paper Section 2, pruning and banding): before a tick,
 //    UB = max(every H on the tick's input borders [, 0]) + match * min(rows
 //    left, columns left); the tick is skipped if UB is strictly below
@@ -62,29 +63,32 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Stripe-to-stripe hand-off.  Boundary values and column counts are accessed
-// with relaxed atomics at agent scope, which the hardware serves coherently
-// across CUs and XCDs without cache maintenance.  Ordering: the producer waits
-// for its boundary stores to complete (vmcnt 0) before storing the count; the
-// consumer reads boundary values only after reading a sufficient count.
+// Stripe-to-stripe hand-off.  Producer and consumer usually sit on different
+// XCDs, each with its own L2.  Release/acquire at agent scope would write back
+// and invalidate a whole L2 on every tick (measured: less than half the
+// throughput), so boundary values and column counts are system-scope relaxed
+// atomics, which write through and read past the per-XCD caches.  Ordering:
+// the producer waits for its boundary stores to complete (vmcnt 0) before
+// storing the count; the consumer reads boundary values only after reading a
+// sufficient count.
 __device__ __forceinline__ int2 ld_shared_i2(const int2* p) {
     const unsigned long long v =
-        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
 }
 
 __device__ __forceinline__ void st_shared_i2(int2* p, int2 v) {
     const unsigned long long w = (unsigned long long)(uint32_t)v.x | ((unsigned long long)(uint32_t)v.y << 32);
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ int load_count(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void publish_count(int32_t* p, int32_t v) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Waits until *flag >= need; `seen` caches the last value read.
@@ -387,9 +391,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         int32_t prod_seen = 0;
         int32_t* gbest = p.gbest + pi;
 
-        // Older tasks this one depends on.
+        // Older tasks this one depends on.  Slot reuse: the previous owner of the
+        // slot must have finished writing it, and the task after that owner (its
+        // reader, when the owner is not the last stripe of its band) finished
+        // reading it.  The owner itself is not implied by its successor: the last
+        // stripe of a band has no reader, and its successor (a first stripe) can
+        // finish before it.
         if (task >= p.nslot) {
             int32_t seen = 0;
+            wait_at_least(p.progress + task - p.nslot, kDone, seen);
+            seen = 0;
             wait_at_least(p.progress + task - p.nslot + 1, kDone, seen);
         }
         if (band > 0) {

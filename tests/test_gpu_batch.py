@@ -150,3 +150,22 @@ def test_tuning_is_used(ctx, orc):
         ctx.set_tuning(swmi.TUNE_BATCH, 16, 4)
     with pytest.raises(swmi.SwError):
         ctx.set_tuning(7, 8, 4)
+
+
+def test_batch_slot_reuse_across_problems(ctx, orc):
+    """Regression: a slot is reused only after its previous owner finished writing it.  The last
+    stripe of a problem has no reader, so the task after it can finish first; with few slots
+    (one wave per CU) and many multi-stripe pairs the reuse happens constantly."""
+    rng = np.random.default_rng(77)
+    pairs = []
+    for t in range(700):
+        la, lb = int(rng.integers(520, 2600)), int(rng.integers(40, 260))
+        p = synth.homologous_pair(5000 + t, la, lb, 0.1) if t % 3 == 0 else synth.random_pair(5000 + t, la, lb)
+        pairs.append((p.a.tobytes(), p.b.tobytes()))
+    exp = [orc.sw_score(a, b) for a, b in pairs]
+    for R in (4, 8):
+        for rep in range(2):
+            _case(f"slot reuse R={R} rep={rep}")
+            got = ctx.batch(pairs, rows_per_lane=R, waves_per_cu=1)
+            bad = [i for i, (g, e) in enumerate(zip(got, exp)) if g.key() != e]
+            assert not bad, (R, rep, bad[:5])
