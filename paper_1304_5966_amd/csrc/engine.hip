@@ -524,6 +524,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         // to memory.  Both only grow: a value one tick old is a valid lower bound.
         const bool polls = q > 0 && prod_active;
         int32_t prod_pf = 0;
+        // The stripe's best recorded value and the first stripe row holding it
+        // (wave-uniform; from exact row maxima only).
+        int sb = LOCAL ? 0 : kNeg;
+        int sb_row = 0;
         int gb_pf = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         for (int tau = 0; tau < n_ticks; ++tau) {
@@ -608,6 +612,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 if (lane == 0 && mx > gb) atomicMax(gbest, mx);
             };
 
+            // After row maxima changed: the stripe's best and its first row.
+            auto refresh_sb = [&](const RowBest<R>& rb) {
+                int v = kNeg, r = INT32_MAX;
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (k < M_rows && rb.best[k] > v) {
+                        v = rb.best[k];
+                        r = lane * R + k;
+                    }
+                const int vm = wave_max(v);
+                const unsigned long long bal = __ballot(v == vm);
+                sb = vm;
+                sb_row = __shfl(r, __ffsll((long long)bal) - 1);
+            };
+
             const bool cd_tick = CD && !skip && !slow && pr.track;
             if (skip) {
                 pruned += (unsigned long long)kTick * kWave * R;
@@ -633,9 +652,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     const int wm = wave_max(tmax);
                     if (lane == 0 && wm > gb) atomicMax(gbest, wm);
                 }
-                // A lane whose maximum reached max(running best, target) replays the
-                // tick to find its rows' maxima and their first columns.
-                if (__any(tmax >= L)) {
+                // The tick is replayed to find row maxima and their first columns when a
+                // lane's maximum reached max(running best, target) and either beats the
+                // stripe's best or ties it in a row before the one holding it.  Any cell
+                // that can be the lexicographically first of the optimum passes both
+                // tests; ties in later rows cannot win and are not replayed.
+                const bool need = tmax >= L && (tmax > sb || (tmax == sb && lane * R < sb_row));
+                if (__any(need)) {
                     restore();
                     bool want[R];
 #pragma unroll
@@ -645,6 +668,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     run_tick<R, LOCAL, kExact, false, CD>(s, rb, cols, c, want);
                     store_rb(rb);
                     publish_best(rb, want);
+                    refresh_sb(rb);
                 }
             } else {
                 RowBest<R> rb;
@@ -677,6 +701,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     }
                 }
                 store_rb(rb);
+                if (CD) refresh_sb(rb);
             }
 
             // Hand the 64 bottom-row columns of this tick to the stripe below.
