@@ -1,0 +1,113 @@
+"""Full-size pairs on the GPU, checked through properties that hold at any size.
+
+The oracle cannot run 2e13 cells, so the 5 Mbp x 4 Mbp pair is checked by:
+the alignment's score and endpoint equal the score pass's; its CIGAR rescores
+to the score and lands on the endpoint; the planted alignment bounds the score
+from below; and sampled windows of the path are optimal.  The last check rests
+on a fact of affine-gap alignment: cut an optimal path at two points that are
+each reached by an aligned pair; the piece between them is an optimal global
+alignment of its block (a better one, spliced in, would only open the same or
+fewer gaps at the cuts and improve the whole path).  The oracle computes each
+block's global optimum one by one.
+
+A 16 Mbp x 14 Mbp crop of the genome-scale pair (minutes of GPU time) runs
+only with SWMI_FULL_SCALE=1.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_1304_5966_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1304_5966_amd import swmi
+    c = swmi.Context(0)
+    yield c
+    c.close()
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _check_windows(a, b, al, orc, rng, n_windows=8, span=3000):
+    """Rescore path pieces between ends of aligned runs against the oracle's global optimum."""
+    runs = orc.parse_cigar(al.cigar)
+    i, j, pts = al.start_a, al.start_b, []  # (i, j, run index) after each run of aligned pairs
+    for r, (n, o) in enumerate(runs):
+        if o in "=X":
+            i += n
+            j += n
+            pts.append((i, j, r))
+        elif o == "I":
+            j += n
+        else:
+            i += n
+    assert len(pts) > 4
+    for k in np.sort(rng.choice(len(pts) - 1, size=min(n_windows, len(pts) - 1), replace=False)):
+        i0, j0, r0 = pts[k]
+        m = k + 1
+        while m + 1 < len(pts) and pts[m + 1][0] - i0 <= span and pts[m + 1][1] - j0 <= span:
+            m += 1
+        i1, j1, r1 = pts[m]
+        cig = "".join(f"{n}{o}" for n, o in runs[r0 + 1:r1 + 1])
+        seg, ea, eb = orc.rescore(a[i0:i1], b[j0:j1], 0, 0, cig)
+        assert (ea, eb) == (i1 - i0 - 1, j1 - j0 - 1)
+        opt = orc.global_score(a[i0:i1], b[j0:j1])
+        assert seg == opt, ((i0, j0, i1, j1), seg, opt)
+
+
+def test_config2_alignment_properties(ctx, orc):
+    p = synth.config2()
+    a, b = p.a.tobytes(), p.b.tobytes()
+    _case("config2 score pass")
+    t0 = time.perf_counter()
+    sc = ctx.score(a, b)
+    _case(f"config2 alignment (score pass {time.perf_counter() - t0:.2f} s)")
+    t0 = time.perf_counter()
+    al = ctx.align(a, b)
+    print(f"config2 alignment {al.score} {al.start_a} {al.start_b} {al.end_a} {al.end_b} "
+          f"({time.perf_counter() - t0:.2f} s)", flush=True)
+    assert (al.score, al.end_a, al.end_b) == sc.key()
+    assert orc.rescore(a, b, al.start_a, al.start_b, al.cigar) == (al.score, al.end_a, al.end_b)
+    pl = p.planted[0]
+    planted, _, _ = orc.rescore(a, b, pl.a_off, pl.b_off, pl.transcript.cigar())
+    assert al.score >= planted > 0.9 * pl.a_len
+    _check_windows(a, b, al, orc, np.random.default_rng(2))
+
+
+@pytest.mark.skipif(os.environ.get("SWMI_FULL_SCALE") != "1", reason="genome scale: set SWMI_FULL_SCALE=1")
+def test_config5_crop_alignment_properties(ctx, orc):
+    """The genome-scale pair cropped to A[0, 16 Mbp) x B[0, 14 Mbp) (2.2e14 cells): one library
+    call on the whole 32 x 28 Mbp pair runs longer than a GPU command may stay silent here."""
+    from paper_1304_5966_amd import swmi
+    p = synth.config5()
+    la, lb = 16_000_000, 14_000_000
+    a, b = p.a[:la].tobytes(), p.b[:lb].tobytes()
+    def b_len(tr):
+        return int(sum(n for o, n in zip(tr.ops, tr.lens) if chr(o) in "=XI"))
+    inside = [pl for pl in p.planted if pl.a_off + pl.a_len <= la and pl.b_off + b_len(pl.transcript) <= lb]
+    assert inside
+    _case("config5 crop score pass (running-best pruning)")
+    t0 = time.perf_counter()
+    sc = ctx.score(a, b, prune=swmi.PRUNE_BEST)
+    print(f"config5 crop score {sc} ({time.perf_counter() - t0:.2f} s)", flush=True)
+    _case("config5 crop alignment (running-best pruning in its score pass)")
+    t0 = time.perf_counter()
+    al = ctx.align(a, b, prune=swmi.PRUNE_BEST)
+    print(f"config5 crop alignment {al.score} {al.start_a} {al.start_b} {al.end_a} {al.end_b} "
+          f"({time.perf_counter() - t0:.2f} s)", flush=True)
+    assert (al.score, al.end_a, al.end_b) == sc.key()
+    assert orc.rescore(a, b, al.start_a, al.start_b, al.cigar) == (al.score, al.end_a, al.end_b)
+    for pl in inside:
+        assert al.score >= orc.rescore(a, b, pl.a_off, pl.b_off, pl.transcript.cigar())[0]
+    _check_windows(a, b, al, orc, np.random.default_rng(5))
