@@ -257,7 +257,10 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
 // because that lane works on the same column one step later.  Lane 63's
 // outputs stay shifted (out[m] carries z = (m - 63) * ext).  Instead of per-row
 // maxima the tick returns the lane's exact maximum H (plain domain).
-template <int R>
+//
+// TRACKMAX = false: no running maximum (returns kNeg), for ticks whose cells
+// provably stay below the value that would need it.
+template <int R, bool TRACKMAX>
 __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
     const int ext = c.ext, g = c.open - c.ext;
     const int off = -(c.lane + 1) * ext;  // the carried state belongs to step -1
@@ -272,7 +275,8 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     s.hl += off;
     s.gl += off;
     int z = -c.lane * ext;
-    int acc = kNeg;  // max over the steps so far of (H - z_step), plus the current z
+    int acc = kNeg;
+    int ohl = 0, ogl = 0;  // lane 63's output of the even step, stored with the odd one  // max over the steps so far of (H - z_step), plus the current z
     const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
     uint32_t lo = src[0], hi = src[1];
@@ -298,7 +302,7 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
             int diag = s.hup;
             s.hup = upH;
             int F = upG;
-            acc += ext;
+            if (TRACKMAX) acc += ext;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int Hd = diag + sext_byte(sc[k], i);
@@ -310,11 +314,17 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
                 s.H[k] = Hn;
                 s.E[k] = En;
                 HA[k] = HAn;
-                acc = max(acc, Hn);
+                if (TRACKMAX) acc = max(acc, Hn);
             }
             s.hl = s.H[R - 1];
             s.gl = F;
-            if (c.lane == kWave - 1) c.out[m] = make_int2(s.hl, s.gl);
+            if (i & 1) {  // lane 63's outputs of two steps in one store
+                if (c.lane == kWave - 1)
+                    *reinterpret_cast<int4*>(c.out + m - 1) = make_int4(ohl, ogl, s.hl, s.gl);
+            } else {
+                ohl = s.hl;
+                ogl = s.gl;
+            }
             z += ext;
         }
     }
@@ -328,7 +338,7 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     s.hup -= back;
     s.hl -= back;
     s.gl -= back;
-    return acc - back;
+    return TRACKMAX ? acc - back : kNeg;
 }
 
 // Does task (band, stripe q) of problem `pr` hold any cell of the kept diagonal band?
@@ -355,7 +365,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     // that the hot loop's registers hold only the recurrence.
     __shared__ int lds_best[R][kWave], lds_pos[R][kWave];
     __shared__ int lds_snap[2 * R + 3][kWave];
-    __shared__ int2 out_buf[kTick];
+    __shared__ __attribute__((aligned(16))) int2 out_buf[kTick];
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
     const int lane = threadIdx.x;
 
@@ -549,21 +559,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             c.rel0 = kTick * tau;
 
             bool skip = false;
+            // Can a cell of this tick reach L?  Its H is at most the largest H on the
+            // tick's borders (or 0, where a local path starts) plus match per aligned
+            // pair, and the tick spans 127 columns.  If not, the shifted tick runs
+            // without its running maximum.
+            bool track_max = true;
             if (!slow) {
                 // diagonal band (global recurrence)
                 const int64_t dmax = c.col0 + (kTick - 1) - R0;
                 const int64_t dmin = c.col0 - R0 - (int64_t)kWave * R - (kTick - 2);
                 if (dmax < pr.d_lo || dmin > pr.d_hi) skip = true;
-                if (!skip && pr.prune) {
+                if (!skip && (pr.prune || CD)) {
                     int hm = max(s.hup, in_ring[cur][lane].x);
 #pragma unroll
                     for (int k = 0; k < R; ++k) hm = max(hm, s.H[k]);
                     hm = wave_max(hm);
                     if (LOCAL) hm = max(hm, 0);
-                    const int64_t rows_left = pr.M - R0;
-                    const int64_t cols_left = pr.N - (c.col0 - (kTick - 1));
-                    const int64_t ub = (int64_t)hm + (int64_t)p.match * min(rows_left, cols_left);
-                    skip = ub < (int64_t)L;
+                    if (pr.prune) {
+                        const int64_t rows_left = pr.M - R0;
+                        const int64_t cols_left = pr.N - (c.col0 - (kTick - 1));
+                        const int64_t ub = (int64_t)hm + (int64_t)p.match * min(rows_left, cols_left);
+                        skip = ub < (int64_t)L;
+                    }
+                    track_max = (int64_t)hm + (int64_t)p.match * (2 * kTick - 1) >= (int64_t)L;
                 }
             }
 
@@ -644,7 +662,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
                 snapshot();
-                const int tmax = run_tick_cd<R>(s, cols, c);
+                const int tmax = track_max ? run_tick_cd<R, true>(s, cols, c) : run_tick_cd<R, false>(s, cols, c);
                 if (pr.target > 0) {
                     // Under an external target, ticks below it are not replayed; keep the
                     // largest H seen in the running best (a valid lower bound of the optimum)
