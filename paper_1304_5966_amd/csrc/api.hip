@@ -243,7 +243,46 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1);
     p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
 
+    // Ticket order.  Problems (largest first) go in groups of G; inside a group
+    // the tasks go round-robin over the problems (task s of every problem that
+    // has one, then task s + 1, ...), so consecutive stripes of a problem are up
+    // to G tickets apart and a stripe rarely waits for the one above.  With
+    // G < nslot / 2 every ticket waits only on older tickets (the reader of a
+    // reused slot comes at most G tickets after its owner).
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.n_probs, (p.nslot - 1) / 2));
+    p.tickets.assign((size_t)p.n_tasks, Ticket{});
+    std::vector<int32_t> tick_of((size_t)p.n_tasks);  // task id (task0 + local) -> ticket
+    int64_t k = 0;
+    for (int64_t g0 = 0; g0 < p.n_probs; g0 += G) {
+        const int64_t g1 = std::min(p.n_probs, g0 + G);
+        int64_t most = 0;
+        for (int64_t pi = g0; pi < g1; ++pi) most = std::max(most, p.probs[pi].Q * p.probs[pi].n_bands);
+        for (int64_t s = 0; s < most; ++s)
+            for (int64_t pi = g0; pi < g1; ++pi) {
+                const Prob& pr = p.probs[pi];
+                if (s >= pr.Q * pr.n_bands) continue;
+                Ticket& tk = p.tickets[(size_t)k];
+                tk.pi = (int32_t)pi;
+                tk.local = (int32_t)s;
+                tick_of[(size_t)(pr.task0 + s)] = (int32_t)k;
+                ++k;
+            }
+    }
+    std::vector<int32_t> reader((size_t)p.n_tasks, -1);  // ticket -> ticket of its slot's reader
+    for (int64_t j = 0; j < p.n_tasks; ++j) {
+        Ticket& tk = p.tickets[(size_t)j];
+        const Prob& pr = p.probs[tk.pi];
+        const int64_t band = tk.local / pr.Q, q = tk.local - band * pr.Q;
+        tk.prod = q > 0 ? tick_of[(size_t)(pr.task0 + tk.local - 1)] : -1;
+        tk.left = band > 0 ? tick_of[(size_t)(pr.task0 + tk.local - pr.Q)] : -1;
+        if (q + 1 < pr.Q) reader[(size_t)j] = tick_of[(size_t)(pr.task0 + tk.local + 1)];
+    }
+    for (int64_t j = 0; j < p.n_tasks; ++j)
+        p.tickets[(size_t)j].reuse_reader = j >= p.nslot ? reader[(size_t)(j - p.nslot)] : -1;
+
     size_t off = 0;
+    p.off_tickets = off;
+    off = align_up(off + (size_t)p.n_tasks * sizeof(Ticket), 256);
     p.off_probs = off;
     off = align_up(off + (size_t)p.n_probs * sizeof(Prob), 256);
     p.off_slots = off;
@@ -271,6 +310,8 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
 sw_status swmi::upload_engine_table(sw_context* ctx, const EnginePlan& plan, void* ws) {
     HIP_TRY(hipMemcpyAsync((uint8_t*)ws + plan.off_probs, plan.probs.data(), (size_t)plan.n_probs * sizeof(Prob),
                            hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync((uint8_t*)ws + plan.off_tickets, plan.tickets.data(),
+                           (size_t)plan.n_tasks * sizeof(Ticket), hipMemcpyHostToDevice, ctx->stream));
     return SW_OK;
 }
 
@@ -281,7 +322,14 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     uint8_t* base = (uint8_t*)ws;
     hipStream_t st = ctx->stream;
     HIP_TRY(launch_zero(base + plan.off_zero, plan.zero_bytes, st));
+    // Every ticket may wait only on older tickets (the pipeline's deadlock freedom).
+    for (int64_t k = 0; k < plan.n_tasks; ++k) {
+        const Ticket& t = plan.tickets[(size_t)k];
+        if (t.prod >= k || t.left >= k || t.reuse_reader >= k)
+            return fail(SW_EINTERNAL, "engine plan: ticket %lld waits on a younger ticket", (long long)k);
+    }
     EngineArgs a{};
+    a.tickets = (const Ticket*)(base + plan.off_tickets);
     a.probs = (const Prob*)(base + plan.off_probs);
     a.n_probs = plan.n_probs;
     a.n_tasks = plan.n_tasks;

@@ -136,6 +136,7 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
                            (uint64_t)L.plan.R, (uint64_t)L.plan.wpc, (uint64_t)L.plan.nslot,
                            (uint64_t)L.plan.slot_stride,
                            (uint64_t)L.plan.total, (uint64_t)L.plan.local, (uint64_t)L.plan.off_slots,
+                           (uint64_t)L.plan.off_tickets, (uint64_t)L.plan.off_probs,
                            (uint64_t)L.plan.off_lbuf, (uint64_t)L.plan.off_recs, (uint64_t)L.plan.off_outs,
                            (uint64_t)L.plan.off_zero, (uint64_t)L.plan.zero_bytes, (uint64_t)L.plan.off_gbest,
                            (uint64_t)L.plan.off_pruned, (uint64_t)L.plan.off_misc, (uint64_t)L.off_a,

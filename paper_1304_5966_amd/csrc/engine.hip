@@ -372,17 +372,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     for (;;) {
         uint32_t tk = 0;
         if (lane == 0) tk = atomicAdd(p.ticket, 1u);
-        const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);
+        const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);  // the ticket
         if (task >= p.n_tasks) break;
-        int64_t lo = 0, hi = p.n_probs - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (p.probs[mid].task0 <= task) lo = mid;
-            else hi = mid - 1;
-        }
-        const int64_t pi = lo;
+        const Ticket tkt = p.tickets[task];
+        const int64_t pi = tkt.pi;
         const Prob pr = p.probs[pi];
-        const int64_t t = task - pr.task0;
+        const int64_t t = tkt.local;
         const int64_t band = t / pr.Q;
         const int64_t q = t - band * pr.Q;
         const int64_t c0 = band * pr.W;
@@ -396,26 +391,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         const uint8_t* bcodes = p.b_codes + pr.b_off;
         int2* lbuf = p.lbuf + pr.lbuf_off;
         int2* my_slot = p.slots + (task % p.nslot) * p.slot_stride;
-        const int2* prod_slot = q > 0 ? p.slots + ((task - 1) % p.nslot) * p.slot_stride : nullptr;
-        const int32_t* prod_prog = p.progress + (task - 1);
+        const int2* prod_slot = q > 0 ? p.slots + ((int64_t)tkt.prod % p.nslot) * p.slot_stride : nullptr;
+        const int32_t* prod_prog = p.progress + (q > 0 ? tkt.prod : 0);
         int32_t prod_seen = 0;
         int32_t* gbest = p.gbest + pi;
 
-        // Older tasks this one depends on.  Slot reuse: the previous owner of the
-        // slot must have finished writing it, and the task after that owner (its
-        // reader, when the owner is not the last stripe of its band) finished
-        // reading it.  The owner itself is not implied by its successor: the last
-        // stripe of a band has no reader, and its successor (a first stripe) can
-        // finish before it.
+        // Older tickets this one depends on.  Slot reuse: the previous owner of the
+        // slot must have finished writing it, and that owner's reader (if the
+        // owner is not the last stripe of its band) finished reading it.  The
+        // owner itself is not implied by its reader's completion: the reader can
+        // finish only after the owner's last column, but a last stripe has no
+        // reader at all.
         if (task >= p.nslot) {
             int32_t seen = 0;
             wait_at_least(p.progress + task - p.nslot, kDone, seen);
-            seen = 0;
-            wait_at_least(p.progress + task - p.nslot + 1, kDone, seen);
+            if (tkt.reuse_reader >= 0) {
+                seen = 0;
+                wait_at_least(p.progress + tkt.reuse_reader, kDone, seen);
+            }
         }
         if (band > 0) {
             int32_t seen = 0;
-            wait_at_least(p.progress + task - pr.Q, kDone, seen);
+            wait_at_least(p.progress + tkt.left, kDone, seen);
         }
         const bool left_active = band > 0 && task_active(pr, band - 1, q, R);
 
@@ -431,7 +428,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 r.pad = 0;
                 r.row = R0;
                 r.col = -1;
-                p.recs[task] = r;
+                p.recs[pr.task0 + t] = r;
             }
             if (capture)
                 for (int64_t row = R0 + lane; row < R1; row += kWave) st_shared_i2(lbuf + row, make_int2(kNeg, kNeg));
@@ -762,7 +759,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 r.pad = 0;
                 r.row = R0 + (int64_t)src * R + rk;
                 r.col = rp;
-                p.recs[task] = r;
+                p.recs[pr.task0 + t] = r;
                 if (pruned) atomicAdd(p.pruned + pi, pruned);
             }
         }

@@ -64,8 +64,9 @@ struct EnginePlan {
     bool local = true;
     int64_t n_probs = 0, n_tasks = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;
     std::vector<Prob> probs;
+    std::vector<Ticket> tickets;
     std::vector<int64_t> order;  // order[k] = index in the spec list of probs[k]
-    size_t off_probs = 0, off_slots = 0, off_lbuf = 0, off_recs = 0, off_outs = 0;
+    size_t off_tickets = 0, off_probs = 0, off_slots = 0, off_lbuf = 0, off_recs = 0, off_outs = 0;
     size_t off_zero = 0, off_prog = 0, off_gbest = 0, off_pruned = 0, off_misc = 0;
     size_t zero_bytes = 0, total = 0;
 };

@@ -52,7 +52,20 @@ struct TaskRec {
     int64_t col;
 };
 
+// Ticket k of a launch (tickets are taken in order by the resident waves).
+// Tasks of different problems are interleaved so that a stripe's producer is
+// usually far ahead when the stripe starts.  All referenced tickets are older.
+struct Ticket {
+    int32_t pi;            // problem (index into the table)
+    int32_t local;         // task index inside the problem: band * Q + stripe
+    int32_t prod;          // ticket of the stripe above in the same band (-1 for the first stripe)
+    int32_t left;          // ticket of the same stripe in the previous band (-1 in band 0)
+    int32_t reuse_reader;  // reader of the slot this ticket reuses (ticket - nslot's consumer), -1 if none
+    int32_t pad[3];
+};
+
 struct EngineArgs {
+    const Ticket* tickets;
     const Prob* probs;
     int64_t n_probs;
     int64_t n_tasks;
