@@ -24,8 +24,10 @@
 //    v_perm_b32 with four column codes as selector yields four score bytes,
 //    consumed by sign-extended byte-select adds.
 //  * Columns are cut into bands of W; a task is (problem, band, stripe), taken
-//    from an in-order ticket counter (problems in decreasing size, then band,
-//    then stripe).  A task only waits on older tasks: the stripe above in the
+//    from an in-order ticket counter through a host-built table (problems in
+//    decreasing size; the tasks of a group of problems interleaved, each
+//    problem's in band, then stripe order).  A task only waits on older
+//    tickets: the stripe above in the
 //    same band (its bottom row streamed through a global slot with a published
 //    column count), the same stripe in the previous band (its right boundary
 //    H,E per row) and the two tasks that last wrote and read the slot being
