@@ -140,6 +140,8 @@ struct TickCtx {
     const int2* in;       // LDS: 64 lane-0 inputs {H, F-candidate} of this tick
     const int2* in_cd;    // the same inputs plus m * ext (column-shifted domain, step m)
     int2* out;            // LDS: 64 lane-63 outputs
+    const uint32_t* bring;  // LDS: the tick's column codes, dwords from bbase on (shifted ticks)
+    uintptr_t bbase;        // address of the first staged dword
     int2* lbuf;           // right-boundary store for the next band (capture)
     int32_t* out_h;       // last-row outputs (reconstruction halves)
     int32_t* out_f;
@@ -277,9 +279,10 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     s.hl += off;
     s.gl += off;
     int z = -c.lane * ext;
-    int acc = kNeg;
-    int ohl = 0, ogl = 0;  // lane 63's output of the even step, stored with the odd one  // max over the steps so far of (H - z_step), plus the current z
-    const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
+    int acc = kNeg;        // max over the steps so far of (H - z_step), plus the current z
+    int ohl = 0, ogl = 0;  // lane 63's output of the even step, stored with the odd one
+    // column codes from the LDS copy staged a tick ahead (no memory latency in the loop)
+    const uint32_t* src = c.bring + ((((uintptr_t)first & ~(uintptr_t)3) - c.bbase) >> 2);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
     uint32_t lo = src[0], hi = src[1];
     const int4* in4 = reinterpret_cast<const int4*>(c.in_cd);
@@ -363,6 +366,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     static_assert(LOCAL || !CD, "the shifted domain is for the local recurrence");
     __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
     __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
+    // Column codes of a tick: lane l reads from column col0 - l on, 18 dwords; the
+    // union over lanes is kBring dwords from the dword holding column col0 - 63.
+    constexpr int kBring = 36;
+    __shared__ uint32_t b_ring[CD ? 2 : 1][kBring];
     // Row maxima and the pre-tick snapshot live in LDS (one column per lane) so
     // that the hot loop's registers hold only the recurrence.
     __shared__ int lds_best[R][kWave], lds_pos[R][kWave];
@@ -504,6 +511,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             const int2 v = fetch(0, min(kTick, W));
             in_ring[0][lane] = v;
             if (CD) in_ring_cd[0][lane] = make_int2(v.x + lane * p.ext, v.y + lane * p.ext);
+            if (CD && lane < kBring)
+                b_ring[0][lane] = reinterpret_cast<const uint32_t*>(
+                    ((uintptr_t)(bcodes + c0 - (kTick - 1)) & ~(uintptr_t)3))[lane];
             if (lane == 0) s.hup = h_diag;
         }
         __syncthreads();
@@ -544,6 +554,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             prod_seen = max(prod_seen, prod_pf);
             int2 nxt = make_int2(NEGV, NEGV);
             if (tau + 1 < n_ticks) nxt = fetch(kTick * (tau + 1), min(kTick * (tau + 2), W));
+            uint32_t b_next = 0;  // next tick's column codes (staged at the end of this tick)
+            if (CD && tau + 1 < n_ticks && lane < kBring)
+                b_next = reinterpret_cast<const uint32_t*>(
+                    ((uintptr_t)(bcodes + c0 + (int64_t)kTick * (tau + 1) - (kTick - 1)) & ~(uintptr_t)3))[lane];
             if (polls && tau + 2 < n_ticks) prod_pf = load_count(prod_prog);
             const uint8_t* cols = bcodes + c0 + (int64_t)kTick * tau - lane;
 
@@ -554,6 +568,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                               (capture && kTick * tau - (kTick - 1) <= W - 1 && W - 1 <= kTick * tau + (kTick - 1));
             c.in = in_ring[cur];
             c.in_cd = in_ring_cd[CD ? cur : 0];
+            c.bring = b_ring[CD ? cur : 0];
+            c.bbase = (uintptr_t)(bcodes + c0 + (int64_t)kTick * tau - (kTick - 1)) & ~(uintptr_t)3;
             c.col0 = c0 + (int64_t)kTick * tau;
             c.rel0 = kTick * tau;
 
@@ -660,7 +676,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 s.gl = NEGV;
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
-                snapshot();
+                if (track_max) snapshot();  // without the running maximum there is no replay
                 const int tmax = track_max ? run_tick_cd<R, true>(s, cols, c) : run_tick_cd<R, false>(s, cols, c);
                 if (pr.target > 0) {
                     // Under an external target, ticks below it are not replayed; keep the
@@ -735,6 +751,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             publish_count(p.progress + task, min(kTick * tau + 1, W));
             in_ring[cur ^ 1][lane] = nxt;
             if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + lane * p.ext, nxt.y + lane * p.ext);
+            if (CD && lane < kBring) b_ring[cur ^ 1][lane] = b_next;
             __syncthreads();
         }
 
