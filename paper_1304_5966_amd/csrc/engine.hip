@@ -713,7 +713,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 bool want[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k) want[k] = false;
-                if (slow) run_tick<R, LOCAL, kRun, true, CD>(s, rb, cols, c, want);
+                // Shifted-domain builds take this path only for slow ticks (and, in
+                // principle, untracked problems): the predicated form serves both
+                // and keeps the fast plain loop out of those builds.
+                if (slow || CD) run_tick<R, LOCAL, kRun, true, CD>(s, rb, cols, c, want);
                 else run_tick<R, LOCAL, kRun, false, CD>(s, rb, cols, c, want);
 
                 if (pr.track) {
@@ -728,7 +731,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     if (__any(any)) {
                         // Replay from the snapshot; the replay ends in the same state.
                         restore();
-                        if (slow) run_tick<R, LOCAL, kTrack, true, CD>(s, rb, cols, c, want);
+                        if (slow || CD) run_tick<R, LOCAL, kTrack, true, CD>(s, rb, cols, c, want);
                         else run_tick<R, LOCAL, kTrack, false, CD>(s, rb, cols, c, want);
                         publish_best(rb, want);
                     }
