@@ -148,3 +148,32 @@ def test_learned_mode_is_exact(ctx, orc, tmp_path):
             r = ctx.score(a, b, prune=swmi.PRUNE_LEARNED, threshold=max(T, 1))
             assert r.key() == exp and r.fallback == (1 if exp[0] < max(T, 1) else 0)
     model.close()
+
+
+def test_trained_model_on_evaluation_pairs(ctx):
+    """The committed network on evaluation-seed pairs (shortened to 0.2-0.4 Mbp): learned pruning
+    returns exactly the unpruned results; the cells each mode computes show what it gains."""
+    import torch
+    from paper_1304_5966_amd import swmi, train
+    path = train.DEFAULT_OUT
+    if not os.path.exists(path):
+        pytest.skip("no trained model in the tree")
+    model = swmi.Model(ctx, path)
+    pairs = [synth.config4_pair(i, synth.SEED_CONFIG4_EVAL, 200_000, 400_000) for i in range(8)]
+    d_a, oa, d_b, ob = _dev_pairs(pairs)
+    cells = sum(p.cells for p in pairs)
+    got = {}
+    for name, kw in (("none", dict(prune=swmi.PRUNE_NONE)), ("best", dict(prune=swmi.PRUNE_BEST)),
+                     ("learned", dict(prune=swmi.PRUNE_LEARNED, model=model.handle))):
+        _case(f"trained model, mode {name}")
+        got[name] = ctx.batch_dev(d_a, oa, d_b, ob, **kw)
+    ref = [r.key() for r in got["none"]]
+    for name in ("best", "learned"):
+        assert [r.key() for r in got[name]] == ref, name
+    for r in got["learned"]:
+        assert r.fallback == (r.key()[0] < r.threshold)
+    frac = {k: sum(r.cells_computed for r in v) / cells for k, v in got.items()}
+    print(f"cells computed: {frac}; thresholds {[r.threshold for r in got['learned']]}; "
+          f"scores {[k[0] for k in ref]}", flush=True)
+    assert frac["none"] == 1.0
+    model.close()
