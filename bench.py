@@ -97,7 +97,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the score pass is "
-              f"not sharded across GPUs in this build)", file=sys.stderr)
+              f"not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
