@@ -9,7 +9,11 @@ wavefront pass -> endpoint reduction -> 16-byte result on the host) over the
 flanks; scoring +1 / -3 / open 5 / extend 2, int32).  Prints one JSON line.
 
 Extra legs (reported in the same line, not in ``value``): the same pass with
-block pruning, and the CPU oracle timed on a bounded crop of the same pair.
+block pruning; the whole alignment of the pair (score pass, start pass,
+Myers-Miller reconstruction) timed by phase; the 20 000-pair batch; the
+learned threshold; and the CPU oracle timed on a bounded crop of the same pair.
+``--only batched|learned|align`` runs one leg alone and prints its JSON (for
+profiling a leg by itself).
 """
 from __future__ import annotations
 
@@ -94,6 +98,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--seq-sample", type=int, default=2000)
+    ap.add_argument("--only", choices=("batched", "learned", "align"), default=None,
+                    help="run one extra leg alone and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the score pass is "
@@ -112,6 +118,18 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4, "dispatches": 3}), flush=True)
         return
 
+    opts = dict(rows_per_lane=args.rows_per_lane, waves_per_cu=args.waves_per_cu)
+    if args.only in ("batched", "learned"):
+        ctx = swmi.Context(0)
+        fixed = bool(args.rows_per_lane or args.waves_per_cu)
+        if fixed:  # a fixed shape for the leg's launches instead of the tuner's
+            ctx.set_tuning(swmi.TUNE_BATCH, args.rows_per_lane, args.waves_per_cu)
+        leg = (batched_leg(ctx, torch, swmi, synth, args.seq_sample, not (args.no_tune or fixed))
+               if args.only == "batched"
+               else learned_leg(ctx, torch, swmi, synth, args.learned_pairs))
+        print(json.dumps(leg), flush=True)
+        return
+
     log("generating the 5 Mbp x 4 Mbp pair")
     pair = synth.config2()
     M, N = pair.a.size, pair.b.size
@@ -119,7 +137,9 @@ def main():
     d_a = torch.from_numpy(pair.a).to(dev)
     d_b = torch.from_numpy(pair.b).to(dev)
     ctx = swmi.Context(0)
-    opts = dict(rows_per_lane=args.rows_per_lane, waves_per_cu=args.waves_per_cu)
+    if args.only == "align":
+        print(json.dumps(alignment_leg(ctx, torch, pair, d_a, d_b, opts)), flush=True)
+        return
     tune = None
     if not (args.no_tune or args.rows_per_lane or args.waves_per_cu):
         from paper_1304_5966_amd import autotune
@@ -188,12 +208,54 @@ def main():
         assert r.key() == score, (r, score)
         line["pruned_best"] = {"gcups_eff": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 3),
                                "cells_computed_frac": round(r.cells_computed / cells, 4)}
+        line["alignment"] = alignment_leg(ctx, torch, pair, d_a, d_b, opts)
         line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)
         line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(pair)
     print(json.dumps(line), flush=True)
+
+
+def alignment_leg(ctx, torch, pair, d_a, d_b, opts):
+    """The three phases on the 5 Mbp x 4 Mbp pair: score pass, start pass, reconstruction.
+
+    ``sw_align`` runs all three on host letters (upload included); the start pass is also
+    timed alone through ``sw_start``, and the reconstruction is the remainder."""
+    a, b = pair.a.tobytes(), pair.b.tobytes()
+    M, N = len(a), len(b)
+    log("alignment leg: score pass")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc = ctx.score_dev(d_a, d_b, **opts)
+    t_score = time.perf_counter() - t0
+    log("alignment leg: start pass")
+    t0 = time.perf_counter()
+    sa, sb = ctx.start(a, b, sc.score, sc.end_a, sc.end_b)
+    t_start = time.perf_counter() - t0
+    log("alignment leg: whole alignment")
+    t0 = time.perf_counter()
+    al = ctx.align(a, b, **opts)
+    t_align = time.perf_counter() - t0
+    assert (al.score, al.end_a, al.end_b) == sc.key(), (al, sc)
+    assert (al.start_a, al.start_b) == (sa, sb), (al, sa, sb)
+    la, lb = al.end_a - al.start_a + 1, al.end_b - al.start_b + 1
+    ops = {o: 0 for o in "=XID"}
+    n = 0
+    for ch in al.cigar:
+        if ch.isdigit():
+            n = n * 10 + ord(ch) - 48
+        else:
+            ops[ch] += n
+            n = 0
+    t_rec = max(t_align - t_score - t_start, 0.0)
+    log(f"alignment leg: score {t_score:.2f} s, start {t_start:.2f} s, whole {t_align:.2f} s")
+    return {"workload": "the same 5 Mbp x 4 Mbp pair, score + start + Myers-Miller CIGAR",
+            "score": al.score, "start": [al.start_a, al.start_b], "end": [al.end_a, al.end_b],
+            "rectangle": [la, lb], "cigar_ops": ops, "cigar_runs": sum(1 for ch in al.cigar if not ch.isdigit()),
+            "score_pass_s": round(t_score, 3), "start_pass_s": round(t_start, 3),
+            "align_total_s": round(t_align, 3), "reconstruction_s": round(t_rec, 3),
+            "score_pass_gcups": round(M * N / t_score / 1e9, 1)}
 
 
 def _pack(pairs):
@@ -217,6 +279,9 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     if tune:
         from paper_1304_5966_amd import autotune
         shape = autotune.tune_batch(ctx, d_a, oa, d_b, ob, use_cache=False, log=log, table=table)
+    if shape is None:
+        R, w = ctx.get_tuning(swmi.TUNE_BATCH)
+        shape = {"rows_per_lane": R, "waves_per_cu": w, "tuned": False}
     ws = ctx.workspace(ctx.batch_workspace_size(oa, ob))
     ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws)
     torch.cuda.synchronize()
@@ -226,8 +291,7 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     # the same launch captured as a HIP graph on a context bound to its own stream
     gstream = torch.cuda.Stream()
     gctx = swmi.Context(0, stream=gstream)
-    if shape:
-        gctx.set_tuning(swmi.TUNE_BATCH, shape["rows_per_lane"], shape["waves_per_cu"])
+    gctx.set_tuning(swmi.TUNE_BATCH, shape["rows_per_lane"], shape["waves_per_cu"])
     gws = torch.empty(gctx.batch_workspace_size(oa, ob, graph=True), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     gres = gctx.batch_dev(d_a, oa, d_b, ob, workspace=gws, graph=True)   # capture + first replay
@@ -237,6 +301,14 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     assert [r.key() for r in gres] == [r.key() for r in res]
     gctx.close()
     del gws
+    out = {"workload": "20 000 pairs, lengths log-uniform 100-20 000 bp per side, even pairs homologous "
+                       "(divergence 5-30 %), odd pairs unrelated; one persistent launch",
+           "gcups": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 2), "cells": cells,
+           "graph_replay_gcups": round(cells / dtg / 1e9, 2), "graph_replay_ms": round(dtg * 1000, 2),
+           "engine_shape": shape, "autotune_candidates": table}
+    if seq_sample <= 0:
+        log(f"batched: {cells / dt / 1e9:.1f} GCUPS")
+        return out
     # the same pairs, one score call each (a seeded sample of the pairs, scaled)
     import numpy as np
     rng = np.random.default_rng(1)
@@ -250,14 +322,9 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     for k, i in enumerate(idx):
         assert seq[k].key() == res[i].key(), (i, seq[k], res[i])
     log(f"batched: {cells / dt / 1e9:.1f} GCUPS; per-pair calls: {sample_cells / dts / 1e9:.1f} GCUPS")
-    return {"workload": "20 000 pairs, lengths log-uniform 100-20 000 bp per side, even pairs homologous "
-                        "(divergence 5-30 %), odd pairs unrelated; one persistent launch",
-            "gcups": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 2), "cells": cells,
-            "per_pair_calls_gcups": round(sample_cells / dts / 1e9, 2),
-            "per_pair_sample": int(len(idx)),
-            "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2),
-            "graph_replay_gcups": round(cells / dtg / 1e9, 2), "graph_replay_ms": round(dtg * 1000, 2),
-            "engine_shape": shape, "autotune_candidates": table}
+    out.update({"per_pair_calls_gcups": round(sample_cells / dts / 1e9, 2), "per_pair_sample": int(len(idx)),
+                "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2)})
+    return out
 
 
 def learned_leg(ctx, torch, swmi, synth, n_pairs):

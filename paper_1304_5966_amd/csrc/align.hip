@@ -308,6 +308,14 @@ void split_sub(const Sub& s, const MidResult& r, int64_t g, int64_t h, std::vect
 
 // ------------------------------------------------------------------------ start point
 
+// Rows per lane for banded global passes.  A stripe of 64 R rows starts 64 R
+// columns right of the one above, so across a band W diagonals wide only about
+// W / (64 R) stripes run at once; R = 4 doubles that where 512-row stripes
+// would leave SIMDs without a wave (fewer than 1.5 per SIMD).
+static int banded_rows(const sw_context* ctx, int64_t band_width_sum) {
+    return band_width_sum >= (int64_t)kWave * 8 * 6 * ctx->num_cu ? 8 : 4;
+}
+
 static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, const sw_scoring* sc,
                             int32_t score, int64_t end_a, int64_t end_b, const sw_options* o, int64_t* start_a,
                             int64_t* start_b) {
@@ -325,7 +333,7 @@ static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     const int64_t G = ((int64_t)sc->match * std::min(M, N) - score) / sc->gap_extend;
     ps.d_lo = -G;
     ps.d_hi = G;
-    const int R = o && o->rows_per_lane ? o->rows_per_lane : 8;
+    const int R = o && o->rows_per_lane ? o->rows_per_lane : banded_rows(ctx, 2 * G + 1);
     const int64_t bw = std::max<int64_t>(kTick, ((2 * G + kWave * R + 4 * kTick) / kTick) * kTick * 2);
     const EnginePlan p = plan_engine(ctx, {ps}, false, R, o ? o->waves_per_cu : 0,
                                      o && o->band_width ? o->band_width : (int)std::min<int64_t>(bw, 1 << 30));
@@ -416,8 +424,6 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
     std::vector<Piece> pieces(1);
     pieces[0].is_sub = true;
     pieces[0].sub = Sub{0, M, 0, N, g, g, total_score, true};
-    const int R = o && o->rows_per_lane ? o->rows_per_lane : 8;
-
     for (;;) {
         // GPU level over every sub-problem with enough rows.
         std::vector<size_t> big;
@@ -426,7 +432,14 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
         if (big.empty()) break;
         std::vector<ProbSpec> specs;
         std::vector<MidTask> mids;
-        int64_t out_len = 0, maxband = 0;
+        int64_t out_len = 0, maxband = 0, width_sum = 0;
+        for (size_t bi : big) {
+            const Sub& sb = pieces[bi].sub;
+            int64_t lo, hi;
+            sub_band(sb, sc->match, (int)h, lo, hi);
+            width_sum += 2 * (lo > -kNoBand ? hi - lo + 1 : sb.N);  // both halves
+        }
+        const int R = o && o->rows_per_lane ? o->rows_per_lane : banded_rows(ctx, width_sum);
         for (size_t bi : big) {
             const Sub& sb = pieces[bi].sub;
             int64_t lo, hi;

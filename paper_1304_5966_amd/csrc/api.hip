@@ -200,8 +200,10 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     // three ticks apart, so a band of T ticks keeps all waves busy only while
     // grid * 3 <= T.  32 GiB (of 288 GB HBM) gives 2 Mi columns at 2048 waves.
     const int64_t grid_est = std::max<int64_t>(1, std::min<int64_t>(max_grid, stripes * ((maxN + 63) / 64)));
+    const int64_t G_est = std::max<int64_t>(1, std::min<int64_t>((int64_t)specs.size(), grid_est / 2));
+    const int64_t nslot_est = grid_est + 1 + (G_est > 1 ? 2 * G_est : 0);
     const size_t slot_budget = (size_t)32 << 30;
-    int64_t Wg = (int64_t)(slot_budget / ((size_t)(grid_est + 1) * sizeof(int2))) - (kSlotPad + 2 * kTick);
+    int64_t Wg = (int64_t)(slot_budget / ((size_t)nslot_est * sizeof(int2))) - (kSlotPad + 2 * kTick);
     Wg = std::max<int64_t>(kTick, Wg / kTick * kTick);
     if (band_width) Wg = band_width;
 
@@ -239,19 +241,34 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     p.n_probs = (int64_t)p.probs.size();
     p.n_tasks = task;
     p.lbuf_rows = lrow;
-    p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, task));
-    p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1);
-    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
+    // Tasks holding a cell of their problem's kept band (all of them when unbanded).
+    std::vector<uint8_t> active((size_t)p.n_tasks, 1);
+    int64_t n_active = p.n_tasks;
+    for (const Prob& pr : p.probs) {
+        if (pr.d_lo <= -kNoBand && pr.d_hi >= kNoBand) continue;
+        for (int64_t l = 0; l < pr.Q * pr.n_bands; ++l)
+            if (!task_in_band(pr, l / pr.Q, l % pr.Q, p.R)) {
+                active[(size_t)(pr.task0 + l)] = 0;
+                --n_active;
+            }
+    }
+    p.n_tickets = n_active;
+    p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, n_active));
 
     // Ticket order.  Problems (largest first) go in groups of G; inside a group
     // the tasks go round-robin over the problems (task s of every problem that
     // has one, then task s + 1, ...), so consecutive stripes of a problem are up
-    // to G tickets apart and a stripe rarely waits for the one above.  With
-    // G < nslot / 2 every ticket waits only on older tickets (the reader of a
-    // reused slot comes at most G tickets after its owner).
-    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.n_probs, (p.nslot - 1) / 2));
-    p.tickets.assign((size_t)p.n_tasks, Ticket{});
-    std::vector<int32_t> tick_of((size_t)p.n_tasks);  // task id (task0 + local) -> ticket
+    // to G tickets apart and a stripe rarely waits for the one above.
+    // Slots: ticket k writes slot k mod nslot, which its previous owner's reader
+    // (at most G tickets after that owner) must have finished with.  With one
+    // slot per wave plus 2G, that reader is more than a whole generation of
+    // waves older than k, so the wait is rare; and since nslot > G every ticket
+    // waits only on older tickets.
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.n_probs, (int64_t)p.grid / 2));
+    p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1 + (G > 1 ? 2 * G : 0));
+    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
+    p.tickets.assign((size_t)p.n_tickets, Ticket{});
+    std::vector<int32_t> tick_of((size_t)p.n_tasks, -1);  // task id (task0 + local) -> ticket, -1: none
     int64_t k = 0;
     for (int64_t g0 = 0; g0 < p.n_probs; g0 += G) {
         const int64_t g1 = std::min(p.n_probs, g0 + G);
@@ -260,7 +277,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
         for (int64_t s = 0; s < most; ++s)
             for (int64_t pi = g0; pi < g1; ++pi) {
                 const Prob& pr = p.probs[pi];
-                if (s >= pr.Q * pr.n_bands) continue;
+                if (s >= pr.Q * pr.n_bands || !active[(size_t)(pr.task0 + s)]) continue;
                 Ticket& tk = p.tickets[(size_t)k];
                 tk.pi = (int32_t)pi;
                 tk.local = (int32_t)s;
@@ -268,21 +285,22 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
                 ++k;
             }
     }
-    std::vector<int32_t> reader((size_t)p.n_tasks, -1);  // ticket -> ticket of its slot's reader
-    for (int64_t j = 0; j < p.n_tasks; ++j) {
+    std::vector<int32_t> reader((size_t)p.n_tickets, -1);  // ticket -> ticket of its slot's reader
+    for (int64_t j = 0; j < p.n_tickets; ++j) {
         Ticket& tk = p.tickets[(size_t)j];
         const Prob& pr = p.probs[tk.pi];
         const int64_t band = tk.local / pr.Q, q = tk.local - band * pr.Q;
         tk.prod = q > 0 ? tick_of[(size_t)(pr.task0 + tk.local - 1)] : -1;
         tk.left = band > 0 ? tick_of[(size_t)(pr.task0 + tk.local - pr.Q)] : -1;
+        tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tick_of[(size_t)(pr.task0 + tk.local - pr.Q - 1)] : -1;
         if (q + 1 < pr.Q) reader[(size_t)j] = tick_of[(size_t)(pr.task0 + tk.local + 1)];
     }
-    for (int64_t j = 0; j < p.n_tasks; ++j)
+    for (int64_t j = 0; j < p.n_tickets; ++j)
         p.tickets[(size_t)j].reuse_reader = j >= p.nslot ? reader[(size_t)(j - p.nslot)] : -1;
 
     size_t off = 0;
     p.off_tickets = off;
-    off = align_up(off + (size_t)p.n_tasks * sizeof(Ticket), 256);
+    off = align_up(off + (size_t)p.n_tickets * sizeof(Ticket), 256);
     p.off_probs = off;
     off = align_up(off + (size_t)p.n_probs * sizeof(Prob), 256);
     p.off_slots = off;
@@ -295,7 +313,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     off = align_up(off + (size_t)p.n_probs * sizeof(ScoreOut), 256);
     p.off_zero = off;  // cleared on every launch
     p.off_prog = off;
-    off = align_up(off + (size_t)p.n_tasks * sizeof(int32_t), 256);
+    off = align_up(off + (size_t)p.n_tickets * sizeof(int32_t), 256);
     p.off_gbest = off;
     off = align_up(off + (size_t)p.n_probs * sizeof(int32_t), 256);
     p.off_pruned = off;
@@ -311,7 +329,7 @@ sw_status swmi::upload_engine_table(sw_context* ctx, const EnginePlan& plan, voi
     HIP_TRY(hipMemcpyAsync((uint8_t*)ws + plan.off_probs, plan.probs.data(), (size_t)plan.n_probs * sizeof(Prob),
                            hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipMemcpyAsync((uint8_t*)ws + plan.off_tickets, plan.tickets.data(),
-                           (size_t)plan.n_tasks * sizeof(Ticket), hipMemcpyHostToDevice, ctx->stream));
+                           (size_t)plan.n_tickets * sizeof(Ticket), hipMemcpyHostToDevice, ctx->stream));
     return SW_OK;
 }
 
@@ -323,16 +341,16 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     hipStream_t st = ctx->stream;
     HIP_TRY(launch_zero(base + plan.off_zero, plan.zero_bytes, st));
     // Every ticket may wait only on older tickets (the pipeline's deadlock freedom).
-    for (int64_t k = 0; k < plan.n_tasks; ++k) {
+    for (int64_t k = 0; k < plan.n_tickets; ++k) {
         const Ticket& t = plan.tickets[(size_t)k];
-        if (t.prod >= k || t.left >= k || t.reuse_reader >= k)
+        if (t.prod >= k || t.left >= k || t.reuse_reader >= k || t.corner >= k)
             return fail(SW_EINTERNAL, "engine plan: ticket %lld waits on a younger ticket", (long long)k);
     }
     EngineArgs a{};
     a.tickets = (const Ticket*)(base + plan.off_tickets);
     a.probs = (const Prob*)(base + plan.off_probs);
     a.n_probs = plan.n_probs;
-    a.n_tasks = plan.n_tasks;
+    a.n_tickets = plan.n_tickets;
     a.a_codes = a_codes;
     a.b_codes = b_codes;
     a.match = sc->match;
@@ -352,7 +370,8 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.out_f = out_f;
     const bool cd = plan.local && sc->match + sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
-    HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, (ScoreOut*)(base + plan.off_outs), a.gbest, a.pruned, st));
+    HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
+                          a.pruned, st));
     return SW_OK;
 }
 

@@ -132,7 +132,7 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
         if (!s) return fail(SW_EINVAL, "SW_FLAG_GRAPH needs a context bound to a non-null stream");
         uint64_t key = 0x51ed270b7f4a7c15ull;
         for (uint64_t v : {(uint64_t)(uintptr_t)d_a, (uint64_t)(uintptr_t)d_b, (uint64_t)(uintptr_t)ws, (uint64_t)n,
-                           (uint64_t)L.plan.n_probs, (uint64_t)L.plan.n_tasks, (uint64_t)L.plan.grid,
+                           (uint64_t)L.plan.n_probs, (uint64_t)L.plan.n_tasks, (uint64_t)L.plan.n_tickets, (uint64_t)L.plan.grid,
                            (uint64_t)L.plan.R, (uint64_t)L.plan.wpc, (uint64_t)L.plan.nslot,
                            (uint64_t)L.plan.slot_stride,
                            (uint64_t)L.plan.total, (uint64_t)L.plan.local, (uint64_t)L.plan.off_slots,

@@ -346,17 +346,6 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     return TRACKMAX ? acc - back : kNeg;
 }
 
-// Does task (band, stripe q) of problem `pr` hold any cell of the kept diagonal band?
-__device__ __forceinline__ bool task_active(const Prob& pr, int64_t band, int64_t q, int R) {
-    if (pr.d_lo <= -kNoBand && pr.d_hi >= kNoBand) return true;
-    const int64_t R0 = q * (int64_t)(kWave * R);
-    const int64_t R1 = min(R0 + (int64_t)(kWave * R), pr.M);
-    const int64_t c0 = band * pr.W;
-    const int64_t W = min(pr.W, pr.N - c0);
-    const int64_t dmin = c0 + 1 - R1, dmax = c0 + W - R0 - 1;
-    return !(dmax < pr.d_lo || dmin > pr.d_hi);
-}
-
 // CD: fast ticks of the local recurrence run in the column-shifted domain
 // (run_tick_cd); needs match + ext <= 127 so that s + ext fits the score bytes.
 // OCC: resident waves per SIMD the register allocation is sized for
@@ -382,7 +371,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         uint32_t tk = 0;
         if (lane == 0) tk = atomicAdd(p.ticket, 1u);
         const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);  // the ticket
-        if (task >= p.n_tasks) break;
+        if (task >= p.n_tickets) break;
         const Ticket tkt = p.tickets[task];
         const int64_t pi = tkt.pi;
         const Prob pr = p.probs[pi];
@@ -399,9 +388,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         const uint8_t* acodes = p.a_codes + pr.a_off;
         const uint8_t* bcodes = p.b_codes + pr.b_off;
         int2* lbuf = p.lbuf + pr.lbuf_off;
+        // Neighbour tasks without a ticket hold no cell of the kept band: their
+        // values are -inf (the ticket table says which exist).
+        const bool prod_active = tkt.prod >= 0;
+        const bool left_active = tkt.left >= 0;
         int2* my_slot = p.slots + (task % p.nslot) * p.slot_stride;
-        const int2* prod_slot = q > 0 ? p.slots + ((int64_t)tkt.prod % p.nslot) * p.slot_stride : nullptr;
-        const int32_t* prod_prog = p.progress + (q > 0 ? tkt.prod : 0);
+        const int2* prod_slot = prod_active ? p.slots + ((int64_t)tkt.prod % p.nslot) * p.slot_stride : nullptr;
+        const int32_t* prod_prog = p.progress + (prod_active ? tkt.prod : 0);
         int32_t prod_seen = 0;
         int32_t* gbest = p.gbest + pi;
 
@@ -419,32 +412,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 wait_at_least(p.progress + tkt.reuse_reader, kDone, seen);
             }
         }
-        if (band > 0) {
+        if (left_active) {
             int32_t seen = 0;
             wait_at_least(p.progress + tkt.left, kDone, seen);
         }
-        const bool left_active = band > 0 && task_active(pr, band - 1, q, R);
-
-        if (!task_active(pr, band, q, R)) {
-            // Entirely outside the kept band: only the values the neighbours read.
-            if (lane == 0) {
-                int hlast = kNeg;
-                if (band == 0) hlast = border_h(pr.left_kind, pr.left_open, p.ext, R1);
-                else if (left_active) hlast = ld_shared_i2(lbuf + R1 - 1).x;
-                st_shared_i2(my_slot + kSlotPad - 1, make_int2(hlast, 0));
-                TaskRec r;
-                r.score = kNeg;
-                r.pad = 0;
-                r.row = R0;
-                r.col = -1;
-                p.recs[pr.task0 + t] = r;
-            }
-            if (capture)
-                for (int64_t row = R0 + lane; row < R1; row += kWave) st_shared_i2(lbuf + row, make_int2(kNeg, kNeg));
-            publish_count(p.progress + task, kDone);
-            continue;
-        }
-        const bool prod_active = q > 0 && task_active(pr, band, q - 1, R);
 
         WaveState<R> s;
         const int M_rows = (int)max((int64_t)0, min((int64_t)R, pr.M - row0));
@@ -504,9 +475,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             int h_diag = 0;
             if (q == 0) {
                 h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
-            } else {
+            } else if (prod_active) {
                 wait_at_least(prod_prog, 1, prod_seen);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
+            } else if (band == 0) {
+                h_diag = border_h(pr.left_kind, pr.left_open, p.ext, R0);
+            } else if (tkt.corner >= 0) {
+                // H(R0 - 1, c0 - 1): the last column of the previous band, captured by
+                // the task above-left (no task of that stripe after it writes the row)
+                int32_t seen = 0;
+                wait_at_least(p.progress + tkt.corner, kDone, seen);
+                h_diag = ld_shared_i2(lbuf + R0 - 1).x;
+            } else {
+                h_diag = kNeg;
             }
             const int2 v = fetch(0, min(kTick, W));
             in_ring[0][lane] = v;
@@ -838,7 +819,7 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t words) {
 
 // Per problem: best task record (highest score, then smallest row, then smallest column).
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__ recs, const Prob* __restrict__ probs,
-                                                     int64_t n_probs, ScoreOut* out,
+                                                     int64_t n_probs, int R, ScoreOut* out,
                                                      const unsigned long long* __restrict__ pruned,
                                                      const int32_t* __restrict__ gbest) {
     __shared__ int32_t s_v[256];
@@ -851,6 +832,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
         int32_t bv = INT32_MIN;
         int64_t br = INT64_MAX, bc = INT64_MAX;
         for (int64_t i = t; i < n; i += blockDim.x) {
+            if (!task_in_band(pr, i / pr.Q, i % pr.Q, R)) continue;  // no ticket, no record
             const TaskRec r = recs[pr.task0 + i];
             const int64_t col = r.col < 0 ? INT64_MAX : r.col;
             if (r.score > bv || (r.score == bv && (r.row < br || (r.row == br && col < bc)))) {
@@ -954,10 +936,11 @@ hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_pe
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out, const int32_t* gbest,
-                         const unsigned long long* pruned, hipStream_t st) {
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, int rows_per_lane, ScoreOut* out,
+                         const int32_t* gbest, const unsigned long long* pruned, hipStream_t st) {
     const int blocks = (int)min((int64_t)4096, max((int64_t)1, n_probs));
-    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, out, pruned, gbest);
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, rows_per_lane, out,
+                       pruned, gbest);
     return hipGetLastError();
 }
 

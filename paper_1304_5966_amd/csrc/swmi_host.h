@@ -62,7 +62,7 @@ struct EnginePlan {
     int wpc = 8;  // resident stripe waves per CU the launch is sized for
     int grid = 1;
     bool local = true;
-    int64_t n_probs = 0, n_tasks = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;
+    int64_t n_probs = 0, n_tasks = 0, n_tickets = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;
     std::vector<Prob> probs;
     std::vector<Ticket> tickets;
     std::vector<int64_t> order;  // order[k] = index in the spec list of probs[k]

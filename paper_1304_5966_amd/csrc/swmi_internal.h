@@ -53,33 +53,50 @@ struct TaskRec {
 };
 
 // Ticket k of a launch (tickets are taken in order by the resident waves).
-// Tasks of different problems are interleaved so that a stripe's producer is
-// usually far ahead when the stripe starts.  All referenced tickets are older.
+// Only tasks holding a cell of their problem's kept diagonal band get a
+// ticket; a task without one has no work, and its neighbours read -inf where
+// they would have read its values.  Tasks of different problems are
+// interleaved so that a stripe's producer is usually far ahead when the
+// stripe starts.  All referenced tickets are older.
 struct Ticket {
     int32_t pi;            // problem (index into the table)
     int32_t local;         // task index inside the problem: band * Q + stripe
-    int32_t prod;          // ticket of the stripe above in the same band (-1 for the first stripe)
-    int32_t left;          // ticket of the same stripe in the previous band (-1 in band 0)
+    int32_t prod;          // ticket of the stripe above in the same band (-1: first stripe, or no task)
+    int32_t left;          // ticket of the same stripe in the previous band (-1: band 0, or no task)
     int32_t reuse_reader;  // reader of the slot this ticket reuses (ticket - nslot's consumer), -1 if none
-    int32_t pad[3];
+    int32_t corner;        // without a producer task: ticket of the stripe above in the previous
+                           // band, whose boundary capture holds this task's corner value; else -1
+    int32_t pad[2];
 };
+
+// Does task (band, stripe q) of problem `pr` hold any cell of the kept
+// diagonal band, with stripes of 64 R rows?
+__host__ __device__ inline bool task_in_band(const Prob& pr, int64_t band, int64_t q, int R) {
+    if (pr.d_lo <= -kNoBand && pr.d_hi >= kNoBand) return true;
+    const int64_t R0 = q * (int64_t)(kWave * R);
+    const int64_t R1 = R0 + (int64_t)(kWave * R) < pr.M ? R0 + (int64_t)(kWave * R) : pr.M;
+    const int64_t c0 = band * pr.W;
+    const int64_t W = pr.W < pr.N - c0 ? pr.W : pr.N - c0;
+    const int64_t dmin = c0 + 1 - R1, dmax = c0 + W - R0 - 1;
+    return !(dmax < pr.d_lo || dmin > pr.d_hi);
+}
 
 struct EngineArgs {
     const Ticket* tickets;
     const Prob* probs;
     int64_t n_probs;
-    int64_t n_tasks;
+    int64_t n_tickets;
     const uint8_t* a_codes;
     const uint8_t* b_codes;
     int32_t match, mismatch, open, ext;
     int2* slots;             // nslot rows of slot_stride {H, gap} pairs
     int64_t slot_stride;
     int64_t nslot;
-    int32_t* progress;       // [n_tasks] columns published (kDone when finished)
+    int32_t* progress;       // [n_tickets] columns published (kDone when finished)
     uint32_t* ticket;
     int32_t* gbest;          // [n_probs] running best of each problem
     int2* lbuf;              // {H, E} at the last column of the previous band, per row
-    TaskRec* recs;           // [n_tasks]
+    TaskRec* recs;           // [tasks], at task0 + local; written by ticketed tasks only
     unsigned long long* pruned;  // [n_probs] cells skipped
     int32_t* out_h;          // last-row H of problems with out_off >= 0
     int32_t* out_f;          // last-row F (deletion-ending) of the same
@@ -103,8 +120,9 @@ hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const 
 // (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st);
-hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, ScoreOut* out, const int32_t* gbest,
-                         const unsigned long long* pruned, hipStream_t st);
+// rows_per_lane: the launch's R (records of tasks outside a kept band are skipped).
+hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, int rows_per_lane, ScoreOut* out,
+                         const int32_t* gbest, const unsigned long long* pruned, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t st);
 

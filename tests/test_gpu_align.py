@@ -66,13 +66,15 @@ def test_align_small(ctx, orc, div):
         assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
 
 
+@pytest.mark.parametrize("R", [0, 8])
 @pytest.mark.parametrize("la,lb,div", [(3000, 2900, 0.05), (5200, 4100, 0.1), (2500, 6000, 0.15)])
-def test_align_gpu_levels(ctx, orc, la, lb, div):
-    """Large enough that the top Myers-Miller levels run on the GPU."""
+def test_align_gpu_levels(ctx, orc, la, lb, div, R):
+    """Large enough that the top Myers-Miller levels run on the GPU; R = 0 lets the
+    library pick rows per lane from the band width (4 on these narrow bands)."""
     p = synth.homologous_pair(la * 7 + lb, la, lb, div)
     a, b = p.a.tobytes(), p.b.tobytes()
-    _case(f"align gpu levels {la}x{lb}")
-    got = ctx.align(a, b)
+    _case(f"align gpu levels {la}x{lb} R={R}")
+    got = ctx.align(a, b, rows_per_lane=R)
     exp = orc.sw_align(a, b)
     assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
     assert orc.rescore(a, b, got.start_a, got.start_b, got.cigar) == (got.score, got.end_a, got.end_b)
