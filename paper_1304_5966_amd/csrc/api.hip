@@ -368,7 +368,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.pruned = (unsigned long long*)(base + plan.off_pruned);
     a.out_h = out_h;
     a.out_f = out_f;
-    const bool cd = plan.local && sc->match + sc->gap_extend <= 127;
+    const bool cd = sc->match + sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
                           a.pruned, st));

@@ -41,11 +41,14 @@
 //    left, columns left); the tick is skipped if UB is strictly below
 //    max(running best, target), or if it lies outside the kept diagonal band.
 //    A skipped tick outputs lower bounds (0 / -inf).  Exact by induction along
-//    an optimal path.  Tasks entirely outside the band do no DP at all.
-//  * First cell of the best score: each lane keeps the running maximum of each
-//    of its rows; a tick that raised a row maximum to at least max(running
-//    best, target) is replayed from a register snapshot to find the first
-//    column holding it.
+//    an optimal path.  Tasks entirely outside the band get no ticket.
+//  * Fast ticks run in a column-shifted domain (run_tick_cd), for both
+//    recurrences, whenever the scores fit it.
+//  * First cell of the best score: a tick whose cells can reach max(running
+//    best, target) (by the border bound above, over the tick's 127 columns)
+//    keeps its lanes' maximum; if a lane reaches it, the tick is replayed from
+//    a snapshot in the plain domain to find each row's maximum and the first
+//    column holding it.  Other ticks keep no maximum.
 #include "swmi_internal.h"
 
 namespace swmi {
@@ -251,20 +254,21 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
     }
 }
 
-// One fast tick of the local recurrence in the column-shifted domain: at step
-// m every value of lane l is stored plus z = (m - l) * ext, i.e. plus ext per
-// DP column.  With g = open - ext the recurrence becomes
+// One fast tick in the column-shifted domain: at step m every value of lane l
+// is stored plus z = (m - l) * ext, i.e. plus ext per DP column.  With
+// g = open - ext the local recurrence becomes
 //     E~ = max(E~', H~' - g, z)    H~ = max(H~diag + (s + ext), E~, F~)
 //     F~(next row) = max(F~, H~ - g) - ext
 // (the row tables already hold s + ext): E's extension cost and the zero floor
 // cost nothing extra, and a value handed to the next lane keeps its offset
-// because that lane works on the same column one step later.  Lane 63's
+// because that lane works on the same column one step later.  The global
+// recurrence (LOCAL = false) is the same without the z term.  Lane 63's
 // outputs stay shifted (out[m] carries z = (m - 63) * ext).  Instead of per-row
 // maxima the tick returns the lane's exact maximum H (plain domain).
 //
 // TRACKMAX = false: no running maximum (returns kNeg), for ticks whose cells
 // provably stay below the value that would need it.
-template <int R, bool TRACKMAX>
+template <int R, bool TRACKMAX, bool LOCAL>
 __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
     const int ext = c.ext, g = c.open - c.ext;
     const int off = -(c.lane + 1) * ext;  // the carried state belongs to step -1
@@ -311,7 +315,7 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int Hd = diag + sext_byte(sc[k], i);
-                const int En = max(max(s.E[k], HA[k]), z);
+                const int En = LOCAL ? max(max(s.E[k], HA[k]), z) : max(s.E[k], HA[k]);
                 const int Hn = max(max(Hd, En), F);
                 const int HAn = Hn - g;
                 F = max(F, HAn) - ext;
@@ -346,13 +350,12 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     return TRACKMAX ? acc - back : kNeg;
 }
 
-// CD: fast ticks of the local recurrence run in the column-shifted domain
-// (run_tick_cd); needs match + ext <= 127 so that s + ext fits the score bytes.
+// CD: fast ticks run in the column-shifted domain (run_tick_cd); needs
+// match + ext <= 127 so that s + ext fits the score bytes.
 // OCC: resident waves per SIMD the register allocation is sized for
 // (512 / OCC VGPRs per lane).
 template <int R, bool LOCAL, bool CD, int OCC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void engine_kernel(EngineArgs p) {
-    static_assert(LOCAL || !CD, "the shifted domain is for the local recurrence");
     __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
     __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
     // Column codes of a tick: lane l reads from column col0 - l on, 18 dwords; the
@@ -641,7 +644,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 sb_row = __shfl(r, __ffsll((long long)bal) - 1);
             };
 
-            const bool cd_tick = CD && !skip && !slow && pr.track;
+            // Untracked problems (halves of the reconstruction) need no maxima at all.
+            if (!pr.track) track_max = false;
+            const bool cd_tick = CD && !skip && !slow;
             if (skip) {
                 pruned += (unsigned long long)kTick * kWave * R;
 #pragma unroll
@@ -658,8 +663,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
                 if (track_max) snapshot();  // without the running maximum there is no replay
-                const int tmax = track_max ? run_tick_cd<R, true>(s, cols, c) : run_tick_cd<R, false>(s, cols, c);
-                if (pr.target > 0) {
+                const int tmax = track_max ? run_tick_cd<R, true, LOCAL>(s, cols, c)
+                                           : run_tick_cd<R, false, LOCAL>(s, cols, c);
+                if (pr.target > 0 && track_max) {
                     // Under an external target, ticks below it are not replayed; keep the
                     // largest H seen in the running best (a valid lower bound of the optimum)
                     // so that a missed target still reports it.
@@ -932,6 +938,7 @@ hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_pe
     const dim3 g(grid);
     if (local && cd) launch_variant<true, true>(args, rows_per_lane, occ, g, st);
     else if (local) launch_variant<true, false>(args, rows_per_lane, occ, g, st);
+    else if (cd) launch_variant<false, true>(args, rows_per_lane, occ, g, st);
     else launch_variant<false, false>(args, rows_per_lane, occ, g, st);
     return hipGetLastError();
 }

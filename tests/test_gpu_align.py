@@ -92,7 +92,8 @@ def test_align_degenerate(ctx, orc):
     _case("align other scoring")
     p = synth.homologous_pair(8, 2600, 2400, 0.1)
     a, b = p.a.tobytes(), p.b.tobytes()
-    for sc in [(2, 1, 3, 1), (1, 1, 2, 2)]:
+    # (100, 120, 140, 30): match + extend > 127, outside the column-shifted domain
+    for sc in [(2, 1, 3, 1), (1, 1, 2, 2), (100, 120, 140, 30)]:
         got = ctx.align(a, b, scoring=sc)
         exp = orc.sw_align(a, b, sc)
         assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
