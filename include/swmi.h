@@ -84,8 +84,12 @@ typedef struct {
 } sw_options;
 
 /* sw_batch_dev: capture the device work of the call in a HIP graph and replay
- * it on later calls with the same pairs, pointers, workspace and options (the
- * context keeps one graph).  Capture needs a non-null stream. */
+ * it on later calls with the same pairs (offsets), pointers, workspace size,
+ * options, scoring, tuning and learned thresholds; other calls capture anew (the
+ * context keeps one graph).  A replay skips the host planning: the graph copies
+ * the launch's tables from pinned host memory kept with it, so the workspace
+ * may be used for other work between replays.  Capture needs a non-null
+ * stream. */
 #define SW_FLAG_GRAPH 1
 
 typedef struct {

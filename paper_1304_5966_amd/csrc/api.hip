@@ -76,7 +76,7 @@ extern "C" sw_status sw_context_destroy(sw_context* ctx) {
     else (void)hipDeviceSynchronize();
     for (auto& b : ctx->bufs) (void)hipFree(b.ptr);
     if (ctx->host_misc) (void)hipHostFree(ctx->host_misc);
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    swmi::free_batch_graph(ctx->batch_graph);
     delete ctx;
     return SW_OK;
 }
@@ -184,11 +184,11 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     p.wpc = wpc;
     const int64_t rows_per_stripe = (int64_t)kWave * p.R;
     // Largest-first order keeps the long problems from trailing the launch.
+    std::vector<std::pair<double, size_t>> keyed(specs.size());  // (-cells, index): ties keep input order
+    for (size_t i = 0; i < specs.size(); ++i) keyed[i] = {-(double)specs[i].M * (double)specs[i].N, i};
+    std::sort(keyed.begin(), keyed.end());
     std::vector<size_t> order(specs.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-        return (double)specs[x].M * (double)specs[x].N > (double)specs[y].M * (double)specs[y].N;
-    });
+    for (size_t i = 0; i < specs.size(); ++i) order[i] = keyed[i].second;
     const int64_t max_grid = (int64_t)ctx->num_cu * wpc;
     int64_t stripes = 0, maxN = 64;
     for (const auto& s : specs) {
@@ -244,8 +244,10 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     // Tasks holding a cell of their problem's kept band (all of them when unbanded).
     std::vector<uint8_t> active((size_t)p.n_tasks, 1);
     int64_t n_active = p.n_tasks;
+    bool banded = false;
     for (const Prob& pr : p.probs) {
         if (pr.d_lo <= -kNoBand && pr.d_hi >= kNoBand) continue;
+        banded = true;
         for (int64_t l = 0; l < pr.Q * pr.n_bands; ++l)
             if (!task_in_band(pr, l / pr.Q, l % pr.Q, p.R)) {
                 active[(size_t)(pr.task0 + l)] = 0;
@@ -269,31 +271,46 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
     p.tickets.assign((size_t)p.n_tickets, Ticket{});
     std::vector<int32_t> tick_of((size_t)p.n_tasks, -1);  // task id (task0 + local) -> ticket, -1: none
+    std::vector<int32_t> ntask((size_t)p.n_probs);         // tasks per problem (compact copy for the loops)
+    for (int64_t pi = 0; pi < p.n_probs; ++pi) ntask[(size_t)pi] = (int32_t)(p.probs[pi].Q * p.probs[pi].n_bands);
     int64_t k = 0;
+    std::vector<int32_t> live;  // problems of the group with a task s, in table order
     for (int64_t g0 = 0; g0 < p.n_probs; g0 += G) {
         const int64_t g1 = std::min(p.n_probs, g0 + G);
-        int64_t most = 0;
-        for (int64_t pi = g0; pi < g1; ++pi) most = std::max(most, p.probs[pi].Q * p.probs[pi].n_bands);
-        for (int64_t s = 0; s < most; ++s)
-            for (int64_t pi = g0; pi < g1; ++pi) {
-                const Prob& pr = p.probs[pi];
-                if (s >= pr.Q * pr.n_bands || !active[(size_t)(pr.task0 + s)]) continue;
-                Ticket& tk = p.tickets[(size_t)k];
-                tk.pi = (int32_t)pi;
-                tk.local = (int32_t)s;
-                tick_of[(size_t)(pr.task0 + s)] = (int32_t)k;
-                ++k;
+        live.clear();
+        for (int64_t pi = g0; pi < g1; ++pi)
+            if (ntask[(size_t)pi] > 0) live.push_back((int32_t)pi);
+        for (int32_t s = 0; !live.empty(); ++s) {
+            size_t keep = 0;
+            for (const int32_t pi : live) {
+                const int64_t id = p.probs[pi].task0 + s;
+                if (!banded || active[(size_t)id]) {
+                    Ticket& tk = p.tickets[(size_t)k];
+                    tk.pi = pi;
+                    tk.local = s;
+                    tick_of[(size_t)id] = (int32_t)k;
+                    ++k;
+                }
+                if (s + 1 < ntask[(size_t)pi]) live[keep++] = pi;
             }
+            live.resize(keep);
+        }
     }
+    // Links, problem by problem (tick_of read in order).
     std::vector<int32_t> reader((size_t)p.n_tickets, -1);  // ticket -> ticket of its slot's reader
-    for (int64_t j = 0; j < p.n_tickets; ++j) {
-        Ticket& tk = p.tickets[(size_t)j];
-        const Prob& pr = p.probs[tk.pi];
-        const int64_t band = tk.local / pr.Q, q = tk.local - band * pr.Q;
-        tk.prod = q > 0 ? tick_of[(size_t)(pr.task0 + tk.local - 1)] : -1;
-        tk.left = band > 0 ? tick_of[(size_t)(pr.task0 + tk.local - pr.Q)] : -1;
-        tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tick_of[(size_t)(pr.task0 + tk.local - pr.Q - 1)] : -1;
-        if (q + 1 < pr.Q) reader[(size_t)j] = tick_of[(size_t)(pr.task0 + tk.local + 1)];
+    for (int64_t pi = 0; pi < p.n_probs; ++pi) {
+        const Prob& pr = p.probs[pi];
+        const int32_t* tof = tick_of.data() + pr.task0;
+        for (int64_t l = 0; l < ntask[(size_t)pi]; ++l) {
+            const int32_t j = tof[l];
+            if (j < 0) continue;
+            Ticket& tk = p.tickets[(size_t)j];
+            const int64_t band = l / pr.Q, q = l - band * pr.Q;
+            tk.prod = q > 0 ? tof[l - 1] : -1;
+            tk.left = band > 0 ? tof[l - pr.Q] : -1;
+            tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tof[l - pr.Q - 1] : -1;
+            if (q + 1 < pr.Q) reader[(size_t)j] = tof[l + 1];
+        }
     }
     for (int64_t j = 0; j < p.n_tickets; ++j)
         p.tickets[(size_t)j].reuse_reader = j >= p.nslot ? reader[(size_t)(j - p.nslot)] : -1;

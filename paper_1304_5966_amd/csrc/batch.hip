@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
+#include <new>
 #include <vector>
 
 #include "swmi.h"
@@ -106,81 +108,28 @@ sw_status batch_device_work(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     return launch_engine_kernels(ctx, L.plan, base + L.off_a, base + L.off_b, sc, base + L.off_eng, nullptr, nullptr);
 }
 
-sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
-                    BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out, bool graph) {
-    if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+// Host copy of the encode table: source offset, destination, length per pair, for a then b.
+void fill_tab(const BatchLayout& L, int32_t n, int64_t* h) {
+    std::copy(L.a_src.begin(), L.a_src.end(), h);
+    std::copy(L.a_dst.begin(), L.a_dst.end(), h + n);
+    std::copy(L.a_len.begin(), L.a_len.end(), h + 2 * (size_t)n);
+    std::copy(L.b_src.begin(), L.b_src.end(), h + 3 * (size_t)n);
+    std::copy(L.b_dst.begin(), L.b_dst.end(), h + 4 * (size_t)n);
+    std::copy(L.b_len.begin(), L.b_len.end(), h + 5 * (size_t)n);
+}
+
+void clear_out(sw_score_result* out, int32_t n) {
     for (int32_t p = 0; p < n; ++p) {
         std::memset(&out[p], 0, sizeof out[p]);
         out[p].end_a = out[p].end_b = -1;
     }
-    if (L.specs.empty()) return SW_OK;
-    uint8_t* base = (uint8_t*)ws;
-    hipStream_t s = ctx->stream;
-    int64_t* tab = (int64_t*)(base + L.off_tab);
-    std::vector<int64_t> h_tab((size_t)n * 6);
-    std::copy(L.a_src.begin(), L.a_src.end(), h_tab.begin());
-    std::copy(L.a_dst.begin(), L.a_dst.end(), h_tab.begin() + n);
-    std::copy(L.a_len.begin(), L.a_len.end(), h_tab.begin() + 2 * (size_t)n);
-    std::copy(L.b_src.begin(), L.b_src.end(), h_tab.begin() + 3 * (size_t)n);
-    std::copy(L.b_dst.begin(), L.b_dst.end(), h_tab.begin() + 4 * (size_t)n);
-    std::copy(L.b_len.begin(), L.b_len.end(), h_tab.begin() + 5 * (size_t)n);
-    // tables go in before every launch (also before a graph replay)
-    HIP_TRY(hipMemcpyAsync(tab, h_tab.data(), h_tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    sw_status st = upload_engine_table(ctx, L.plan, base + L.off_eng);
-    if (st != SW_OK) return st;
-    if (graph) {
-        if (!s) return fail(SW_EINVAL, "SW_FLAG_GRAPH needs a context bound to a non-null stream");
-        uint64_t key = 0x51ed270b7f4a7c15ull;
-        for (uint64_t v : {(uint64_t)(uintptr_t)d_a, (uint64_t)(uintptr_t)d_b, (uint64_t)(uintptr_t)ws, (uint64_t)n,
-                           (uint64_t)L.plan.n_probs, (uint64_t)L.plan.n_tasks, (uint64_t)L.plan.n_tickets, (uint64_t)L.plan.grid,
-                           (uint64_t)L.plan.R, (uint64_t)L.plan.wpc, (uint64_t)L.plan.nslot,
-                           (uint64_t)L.plan.slot_stride,
-                           (uint64_t)L.plan.total, (uint64_t)L.plan.local, (uint64_t)L.plan.off_slots,
-                           (uint64_t)L.plan.off_tickets, (uint64_t)L.plan.off_probs,
-                           (uint64_t)L.plan.off_lbuf, (uint64_t)L.plan.off_recs, (uint64_t)L.plan.off_outs,
-                           (uint64_t)L.plan.off_zero, (uint64_t)L.plan.zero_bytes, (uint64_t)L.plan.off_gbest,
-                           (uint64_t)L.plan.off_pruned, (uint64_t)L.plan.off_misc, (uint64_t)L.off_a,
-                           (uint64_t)L.off_b, (uint64_t)L.off_tab, (uint64_t)L.off_flags, (uint64_t)L.off_eng,
-                           (uint64_t)L.total, (uint64_t)L.a_bytes, (uint64_t)L.b_bytes,
-                           (uint64_t)sc->match, (uint64_t)sc->mismatch, (uint64_t)sc->gap_open,
-                           (uint64_t)sc->gap_extend})
-            key = mix(key, v);
-        if (!ctx->graph_exec || ctx->graph_key != key) {
-            if (ctx->graph_exec) {
-                HIP_TRY(hipGraphExecDestroy(ctx->graph_exec));
-                ctx->graph_exec = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            st = batch_device_work(ctx, d_a, d_b, n, sc, L, base);
-            hipError_t e = hipStreamEndCapture(s, &g);
-            if (st != SW_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return st;
-            }
-            if (e != hipSuccess) return fail(SW_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                ctx->graph_exec = nullptr;
-                return fail(SW_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-            }
-            ctx->graph_key = key;
-        }
-        HIP_TRY(hipGraphLaunch(ctx->graph_exec, s));
-    } else {
-        if ((st = batch_device_work(ctx, d_a, d_b, n, sc, L, base)) != SW_OK) return st;
-    }
-    uint8_t* eng = base + L.off_eng;
-    unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
-    std::vector<ScoreOut> so((size_t)L.plan.n_probs);
-    unsigned long long flags[2];
-    HIP_TRY(hipMemcpyAsync(flags, bad, sizeof flags, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(so.data(), eng + L.plan.off_outs, so.size() * sizeof(ScoreOut), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+}
+
+// Per-pair results from the launch's bad-letter flags and per-problem outputs.
+sw_status collect(const BatchLayout& L, const unsigned long long* flags, const ScoreOut* so, sw_score_result* out) {
     if (flags[0]) return fail(SW_EINVAL, "seqs_a: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[0]);
     if (flags[1]) return fail(SW_EINVAL, "seqs_b: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[1]);
-    for (size_t k = 0; k < so.size(); ++k) {
+    for (size_t k = 0; k < (size_t)L.plan.n_probs; ++k) {
         const size_t spec = (size_t)L.plan.order[k];
         const int32_t p = L.pair_of_spec[spec];
         if (so[k].status) return fail(SW_EINTERNAL, "batch: endpoint of pair %d was not tracked", p);
@@ -195,7 +144,143 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
     return SW_OK;
 }
 
+sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
+                    BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out) {
+    if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+    clear_out(out, n);
+    if (L.specs.empty()) return SW_OK;
+    uint8_t* base = (uint8_t*)ws;
+    hipStream_t s = ctx->stream;
+    std::vector<int64_t> h_tab((size_t)n * 6);
+    fill_tab(L, n, h_tab.data());
+    HIP_TRY(hipMemcpyAsync(base + L.off_tab, h_tab.data(), h_tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    sw_status st = upload_engine_table(ctx, L.plan, base + L.off_eng);
+    if (st != SW_OK) return st;
+    if ((st = batch_device_work(ctx, d_a, d_b, n, sc, L, base)) != SW_OK) return st;
+    std::vector<ScoreOut> so((size_t)L.plan.n_probs);
+    unsigned long long flags[2];
+    HIP_TRY(hipMemcpyAsync(flags, base + L.off_flags, sizeof flags, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(so.data(), base + L.off_eng + L.plan.off_outs, so.size() * sizeof(ScoreOut),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return collect(L, flags, so.data(), out);
+}
+
+// A captured batch: the graph copies the tables from pinned host memory owned
+// here, then runs the device work.  A later call whose inputs hash to the same
+// key replays it without planning.
+struct BatchGraph {
+    uint64_t key = 0;
+    hipGraphExec_t exec = nullptr;
+    BatchLayout L;
+    void* pinned = nullptr;  // tables | results (flags, per-problem outputs)
+    size_t off_probs = 0, off_tickets = 0, off_flags = 0, off_outs = 0;
+};
+
+void destroy(BatchGraph* g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    delete g;
+}
+
+// Everything a batch launch depends on: pointers, workspace, pairs, options,
+// scoring, the context's tuning and the per-pair thresholds.
+uint64_t inputs_key(const sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, void* ws, size_t ws_bytes,
+                    const std::vector<int64_t>& as, const std::vector<int64_t>& al, const std::vector<int64_t>& bs,
+                    const std::vector<int64_t>& bl, const sw_scoring* sc, const sw_options* o,
+                    const std::vector<int32_t>& T) {
+    uint64_t key = 0x51ed270b7f4a7c15ull;
+    for (uint64_t v : {(uint64_t)(uintptr_t)d_a, (uint64_t)(uintptr_t)d_b, (uint64_t)(uintptr_t)ws, (uint64_t)ws_bytes,
+                       (uint64_t)as.size(), (uint64_t)sc->match, (uint64_t)sc->mismatch, (uint64_t)sc->gap_open,
+                       (uint64_t)sc->gap_extend, (uint64_t)o->prune_mode, (uint64_t)(uint32_t)o->threshold,
+                       (uint64_t)(uintptr_t)o->model, (uint64_t)o->rows_per_lane, (uint64_t)o->waves_per_cu,
+                       (uint64_t)o->band_width, (uint64_t)o->flags})
+        key = mix(key, v);
+    for (int c = 0; c < 4; ++c) key = mix(mix(key, (uint64_t)ctx->tuned_R[c]), (uint64_t)ctx->tuned_wpc[c]);
+    for (size_t i = 0; i < as.size(); ++i)
+        key = mix(mix(mix(mix(key, (uint64_t)as[i]), (uint64_t)al[i]), (uint64_t)bs[i]), (uint64_t)bl[i]);
+    for (int32_t t : T) key = mix(key, (uint64_t)(uint32_t)t);
+    return key;
+}
+
+sw_status run_batch_graph(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, const std::vector<int64_t>& as,
+                          const std::vector<int64_t>& al, const std::vector<int64_t>& bs,
+                          const std::vector<int64_t>& bl, const sw_scoring* sc, const sw_options* o,
+                          const std::vector<int32_t>& T, void* ws, size_t ws_bytes, sw_score_result* out) {
+    hipStream_t s = ctx->stream;
+    if (!s) return fail(SW_EINVAL, "SW_FLAG_GRAPH needs a context bound to a non-null stream");
+    const int32_t n = (int32_t)as.size();
+    const uint64_t key = inputs_key(ctx, d_a, d_b, ws, ws_bytes, as, al, bs, bl, sc, o, T);
+    BatchGraph* g = (BatchGraph*)ctx->batch_graph;
+    if (!g || g->key != key) {
+        destroy(g);
+        ctx->batch_graph = nullptr;
+        g = new (std::nothrow) BatchGraph();
+        if (!g) return fail(SW_ENOMEM, "batch graph: out of host memory");
+        std::unique_ptr<BatchGraph, void (*)(BatchGraph*)> hold(g, destroy);
+        sw_status st = make_layout(ctx, as, al, bs, bl, sc, o, T.empty() ? nullptr : &T, g->L);
+        if (st != SW_OK) return st;
+        const BatchLayout& L = g->L;
+        if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+        const size_t tab_bytes = align_up((size_t)n * 6 * sizeof(int64_t), 256);
+        g->off_probs = tab_bytes;
+        g->off_tickets = g->off_probs + align_up((size_t)L.plan.n_probs * sizeof(Prob), 256);
+        g->off_flags = g->off_tickets + align_up((size_t)L.plan.n_tickets * sizeof(Ticket), 256);
+        g->off_outs = g->off_flags + 256;
+        const size_t bytes = g->off_outs + (size_t)L.plan.n_probs * sizeof(ScoreOut) + 256;
+        HIP_TRY(hipHostMalloc(&g->pinned, bytes, hipHostMallocDefault));
+        uint8_t* hp = (uint8_t*)g->pinned;
+        fill_tab(L, n, (int64_t*)hp);
+        std::memcpy(hp + g->off_probs, L.plan.probs.data(), (size_t)L.plan.n_probs * sizeof(Prob));
+        std::memcpy(hp + g->off_tickets, L.plan.tickets.data(), (size_t)L.plan.n_tickets * sizeof(Ticket));
+        if (!L.specs.empty()) {
+            uint8_t* base = (uint8_t*)ws;
+            uint8_t* eng = base + L.off_eng;
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipMemcpyAsync(base + L.off_tab, hp, (size_t)n * 6 * sizeof(int64_t),
+                                          hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(eng + L.plan.off_probs, hp + g->off_probs, (size_t)L.plan.n_probs * sizeof(Prob),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(eng + L.plan.off_tickets, hp + g->off_tickets,
+                                   (size_t)L.plan.n_tickets * sizeof(Ticket), hipMemcpyHostToDevice, s);
+            st = e == hipSuccess ? batch_device_work(ctx, d_a, d_b, n, sc, g->L, base)
+                                 : fail(SW_EDEVICE, "batch graph: table copy: %s", hipGetErrorString(e));
+            e = hipStreamEndCapture(s, &graph);
+            if (st != SW_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SW_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                g->exec = nullptr;
+                return fail(SW_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+        }
+        g->key = key;
+        ctx->batch_graph = hold.release();
+    }
+    const BatchLayout& L = g->L;
+    clear_out(out, n);
+    if (L.specs.empty()) return SW_OK;
+    uint8_t* base = (uint8_t*)ws;
+    uint8_t* hp = (uint8_t*)g->pinned;
+    HIP_TRY(hipGraphLaunch(g->exec, s));
+    HIP_TRY(hipMemcpyAsync(hp + g->off_flags, base + L.off_flags, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hp + g->off_outs, base + L.off_eng + L.plan.off_outs,
+                           (size_t)L.plan.n_probs * sizeof(ScoreOut), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return collect(L, (const unsigned long long*)(hp + g->off_flags), (const ScoreOut*)(hp + g->off_outs), out);
+}
+
 }  // namespace
+
+void swmi::free_batch_graph(void* g) { destroy((BatchGraph*)g); }
 
 static sw_status pairs_of(const int64_t* offs_a, const int64_t* offs_b, int32_t n, std::vector<int64_t>& as,
                           std::vector<int64_t>& al, std::vector<int64_t>& bs, std::vector<int64_t>& bl) {
@@ -273,11 +358,14 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
             }
         }
     }
-    BatchLayout L;
-    sw_status st = make_layout(ctx, as, al, bs, bl, sc, o, T.empty() ? nullptr : &T, L);
-    if (st != SW_OK) return st;
-    const bool graph = o && (o->flags & SW_FLAG_GRAPH);
-    if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out, graph)) != SW_OK) return st;
+    sw_status st;
+    if (o && (o->flags & SW_FLAG_GRAPH)) {
+        if ((st = run_batch_graph(ctx, d_a, d_b, as, al, bs, bl, sc, o, T, ws, ws_bytes, out)) != SW_OK) return st;
+    } else {
+        BatchLayout L;
+        if ((st = make_layout(ctx, as, al, bs, bl, sc, o, T.empty() ? nullptr : &T, L)) != SW_OK) return st;
+        if ((st = run_batch(ctx, d_a, d_b, n, sc, L, ws, ws_bytes, out)) != SW_OK) return st;
+    }
     if (!o || o->prune_mode != SW_PRUNE_LEARNED) return SW_OK;
     std::vector<int64_t> as2, al2, bs2, bl2;
     std::vector<int32_t> idx, T2;
@@ -302,7 +390,7 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
     if ((st = make_layout(ctx, as2, al2, bs2, bl2, sc, &ob2, &T2, L2)) != SW_OK) return st;
     if (L2.total > ws_bytes) return fail(SW_ENOMEM, "batch fallback: workspace too small");
     std::vector<sw_score_result> r2(idx.size());
-    if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data(), false)) != SW_OK)
+    if ((st = run_batch(ctx, d_a, d_b, (int32_t)idx.size(), sc, L2, ws, ws_bytes, r2.data())) != SW_OK)
         return st;
     for (size_t k = 0; k < idx.size(); ++k) {
         if (r2[k].score < T2[k])

@@ -26,15 +26,18 @@ sw_status predict_thresholds(sw_context* ctx, const sw_model* m, const uint8_t* 
                              const uint8_t* d_b, const int64_t* offs_b, int32_t n, void* ws, size_t ws_bytes,
                              std::vector<int32_t>& T);
 
+// Releases a context's captured batch launch (sw_context::batch_graph).
+void free_batch_graph(void* g);
+
 }  // namespace swmi
 
 struct sw_context {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 0;
-    // captured batch launch (SW_FLAG_GRAPH): replayed while the key matches
-    hipGraphExec_t graph_exec = nullptr;
-    uint64_t graph_key = 0;
+    // captured batch launch (SW_FLAG_GRAPH) with its layout and pinned tables
+    // (batch.hip), replayed while the call's inputs match its key
+    void* batch_graph = nullptr;
     // autotuned shapes per workload class (0 = not tuned): rows per lane, waves per CU
     int tuned_R[4] = {0, 0, 0, 0};
     int tuned_wpc[4] = {0, 0, 0, 0};

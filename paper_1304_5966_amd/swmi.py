@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections.abc import Sequence
 from dataclasses import dataclass
 
 import numpy as np
@@ -169,6 +170,38 @@ def _score_of(r: ScoreResult) -> Score:
     return Score(r.score, r.end_a, r.end_b, r.cells_computed, r.threshold, r.fallback)
 
 
+_SCORE_DTYPE = np.dtype([("score", "<i4"), ("threshold", "<i4"), ("end_a", "<i8"), ("end_b", "<i8"),
+                         ("cells_computed", "<i8"), ("fallback", "<i4"), ("reserved", "<i4")])
+assert _SCORE_DTYPE.itemsize == ctypes.sizeof(ScoreResult)
+
+
+class BatchResults(Sequence):
+    """Per-pair results of a batch call: a numpy view of the library's result
+    array (``.array``), turned into Score objects on access."""
+
+    def __init__(self, raw, n: int):
+        self._raw = raw  # keeps the ctypes buffer alive
+        self.array = np.frombuffer(raw, dtype=_SCORE_DTYPE, count=n) if n else np.zeros(0, _SCORE_DTYPE)
+
+    def __len__(self):
+        return len(self.array)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        r = self.array[i]
+        return Score(int(r["score"]), int(r["end_a"]), int(r["end_b"]), int(r["cells_computed"]),
+                     int(r["threshold"]), int(r["fallback"]))
+
+    def __eq__(self, other):
+        return list(self) == list(other)
+
+    def keys(self):
+        """(score, end_a, end_b) per pair."""
+        a = self.array
+        return list(zip(a["score"].tolist(), a["end_a"].tolist(), a["end_b"].tolist()))
+
+
 class Context:
     """A library context on one device, bound to a HIP stream (default: torch's current stream)."""
 
@@ -247,7 +280,7 @@ class Context:
         _check(lib.sw_batch(self.handle, _bytes(seqs_a), offs_a.ctypes.data_as(i64p), _bytes(seqs_b),
                             offs_b.ctypes.data_as(i64p), n, ctypes.byref(Scoring(*scoring)),
                             ctypes.byref(_options(**opts)), out))
-        return [_score_of(out[i]) for i in range(n)]
+        return BatchResults(out, n)
 
     def batch_dev(self, d_seqs_a, offs_a, d_seqs_b, offs_b, scoring=DEFAULT_SCORING, workspace=None,
                   **opts):
@@ -257,16 +290,17 @@ class Context:
         n = len(offs_a) - 1
         i64p = ctypes.POINTER(ctypes.c_int64)
         sc, op = Scoring(*scoring), _options(**opts)
-        need = int(lib.sw_batch_workspace_size(self.handle, offs_a.ctypes.data_as(i64p),
-                                               offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc),
-                                               ctypes.byref(op)))
-        ws = workspace if workspace is not None else self.workspace(need)
+        if workspace is None:  # the library checks a caller's workspace itself
+            workspace = self.workspace(int(lib.sw_batch_workspace_size(
+                self.handle, offs_a.ctypes.data_as(i64p), offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc),
+                ctypes.byref(op))))
+        ws = workspace
         out = (ScoreResult * max(n, 1))()
         _check(lib.sw_batch_dev(self.handle, ctypes.c_void_p(d_seqs_a.data_ptr()),
                                 offs_a.ctypes.data_as(i64p), ctypes.c_void_p(d_seqs_b.data_ptr()),
                                 offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc), ctypes.byref(op),
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), out))
-        return [_score_of(out[i]) for i in range(n)]
+        return BatchResults(out, n)
 
     def batch_workspace_size(self, offs_a, offs_b, scoring=DEFAULT_SCORING, **opts) -> int:
         offs_a = np.ascontiguousarray(offs_a, dtype=np.int64)

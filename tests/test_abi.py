@@ -51,3 +51,22 @@ def test_binding_reports_errors_without_gpu():
     if st != swmi.SW_OK:
         assert swmi.lib.sw_last_error()
         assert swmi.lib.sw_score(None, b"A", 1, b"A", 1, None, None, None) == swmi.SW_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libswmi.so not built")
+def test_batch_results_view_matches_the_result_structs():
+    """BatchResults reads the library's sw_score_result array through a numpy view;
+    its field layout must match the C struct field by field."""
+    from paper_1304_5966_amd import swmi
+    raw = (swmi.ScoreResult * 3)()
+    for i, r in enumerate(raw):
+        r.score, r.threshold, r.end_a, r.end_b = 10 * i + 1, i, 1000 + i, 2 ** 40 + i
+        r.cells_computed, r.fallback = 3 ** 30 + i, i % 2
+    res = swmi.BatchResults(raw, 3)
+    assert len(res) == 3
+    assert res[1] == swmi.Score(11, 1001, 2 ** 40 + 1, 3 ** 30 + 1, 1, 1)
+    assert res[-1].key() == (21, 1002, 2 ** 40 + 2)
+    assert [r.key() for r in res] == res.keys() == [(1, 1000, 2 ** 40), (11, 1001, 2 ** 40 + 1),
+                                                   (21, 1002, 2 ** 40 + 2)]
+    assert res[1:] == [res[1], res[2]]
+    assert swmi.BatchResults((swmi.ScoreResult * 1)(), 0) == []

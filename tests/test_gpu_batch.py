@@ -90,6 +90,9 @@ def test_batch_graph_replay(orc):
         d_a, oa, d_b, ob = _packed(first)
         exp = [orc.sw_score(p.a.tobytes(), p.b.tobytes()) for p in first]
         ws = torch.empty(c.batch_workspace_size(oa, ob, graph=True), dtype=torch.uint8, device="cuda")
+        other = [synth.config3_pair(1000 + i) for i in range(40)]
+        d_ao, oao, d_bo, obo = _packed(other)
+        exp_o = [orc.sw_score(p.a.tobytes(), p.b.tobytes()) for p in other]
         torch.cuda.synchronize()
         for rep in range(3):
             _case(f"graph replay {rep}")
@@ -98,6 +101,8 @@ def test_batch_graph_replay(orc):
             _case(f"eager between replays {rep}")
             got = c.batch_dev(d_a, oa, d_b, ob, workspace=ws)
             assert [g.key() for g in got] == exp
+            # another batch's tables overwrite the workspace: the replay copies its own again
+            assert c.batch_dev(d_ao, oao, d_bo, obo, workspace=ws).keys() == exp_o
             torch.cuda.synchronize()
         # Same lengths, different letters, same buffers: the replay must read the new letters.
         second = [synth.homologous_pair(900 + k, p.a.size, p.b.size, 0.15) for k, p in enumerate(first)]
