@@ -536,8 +536,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         for (int tau = 0; tau < n_ticks; ++tau) {
             const int cur = tau & 1;
             prod_seen = max(prod_seen, prod_pf);
+            if (!LOCAL) prod_seen = __builtin_amdgcn_readfirstlane(prod_seen);
+            // The next tick's inputs are loaded now, their latency hidden behind this
+            // tick.  The banded global passes run as a chain of stripes each right
+            // behind its producer: there, if the producer is not far enough yet,
+            // they are loaded after this tick instead, so a stripe trails its
+            // producer by two ticks, not three (the local passes keep the early
+            // load: a late one would expose its latency).
             int2 nxt = make_int2(NEGV, NEGV);
-            if (tau + 1 < n_ticks) nxt = fetch(kTick * (tau + 1), min(kTick * (tau + 2), W));
+            const int need_nxt = min(kTick * (tau + 2), W);
+            const bool nxt_now = tau + 1 < n_ticks && (LOCAL || !polls || prod_seen >= need_nxt);
+            if (nxt_now) nxt = fetch(kTick * (tau + 1), need_nxt);
             uint32_t b_next = 0;  // next tick's column codes (staged at the end of this tick)
             if (CD && tau + 1 < n_ticks && lane < kBring)
                 b_next = reinterpret_cast<const uint32_t*>(
@@ -739,6 +748,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, o);
             }
             publish_count(p.progress + task, min(kTick * tau + 1, W));
+            if (!LOCAL && tau + 1 < n_ticks && !nxt_now) {
+                prod_seen = max(prod_seen, prod_pf);
+                nxt = fetch(kTick * (tau + 1), need_nxt);
+            }
             in_ring[cur ^ 1][lane] = nxt;
             if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + lane * p.ext, nxt.y + lane * p.ext);
             if (CD && lane < kBring) b_ring[cur ^ 1][lane] = b_next;
