@@ -150,6 +150,37 @@ def test_learned_mode_is_exact(ctx, orc, tmp_path):
     model.close()
 
 
+def test_learned_batch_graph_replay(orc, tmp_path):
+    """SW_FLAG_GRAPH in LEARNED mode: the captured batch is keyed on the predicted thresholds too;
+    every replay returns the oracle's results and the eager call's thresholds and fallbacks."""
+    import torch
+    from paper_1304_5966_amd import swmi, train
+    stream = torch.cuda.Stream()
+    c = swmi.Context(0, stream=stream)
+    try:
+        path = str(tmp_path / "m.bin")
+        train.save_model(path, np.zeros(256, np.float32), np.full(256, 0.05, np.float32), _rand_model(7))
+        model = swmi.Model(c, path)
+        pairs = [synth.config3_pair(i) for i in range(60)]
+        d_a, oa, d_b, ob = _dev_pairs(pairs)
+        exp = [orc.sw_score(p.a.tobytes(), p.b.tobytes()) for p in pairs]
+        kw = dict(prune=swmi.PRUNE_LEARNED, model=model.handle)
+        ws = torch.empty(c.batch_workspace_size(oa, ob, graph=True, **kw), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        _case("learned batch, eager")
+        eager = c.batch_dev(d_a, oa, d_b, ob, workspace=ws, **kw)
+        assert eager.keys() == exp
+        marks = [(r.threshold, r.fallback) for r in eager]
+        for rep in range(3):
+            _case(f"learned batch, graph replay {rep}")
+            got = c.batch_dev(d_a, oa, d_b, ob, workspace=ws, graph=True, **kw)
+            assert got.keys() == exp
+            assert [(r.threshold, r.fallback) for r in got] == marks
+        model.close()
+    finally:
+        c.close()
+
+
 def test_trained_model_on_evaluation_pairs(ctx):
     """The committed network on evaluation-seed pairs (shortened to 0.2-0.4 Mbp): learned pruning
     returns exactly the unpruned results; the cells each mode computes show what it gains."""
