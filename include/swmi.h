@@ -193,7 +193,11 @@ sw_status sw_mm_host(const char* a, int64_t len_a, const char* b, int64_t len_b,
 /* sw_batch on device-resident letters: d_seqs_a / d_seqs_b hold the packed
  * letters on the context's device, indexed by the host offset arrays offs_a /
  * offs_b exactly as in sw_batch.  The device workspace (caller-owned, at least
- * sw_batch_workspace_size bytes) holds every intermediate. */
+ * sw_batch_workspace_size bytes) holds every intermediate.
+ * Workspace sizes include the stripe hand-off slots: one per resident wave,
+ * plus up to SWMI_SLOT_ROOM_BYTES more (environment variable, bytes; default
+ * 8 GiB; 0 keeps the minimal ring) where slots are small, so that a batch of
+ * many short pairs rarely waits for a slot to be free. */
 size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b, int32_t n_pairs,
                                const sw_scoring* scoring, const sw_options* options);
 sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, const int64_t* offs_a, const uint8_t* d_seqs_b,

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -167,6 +168,14 @@ sw_status swmi::check_options(const sw_options* o) {
 
 // ------------------------------------------------------------------------ engine plan
 
+// Slot memory a launch may take beyond its minimal ring: SWMI_SLOT_ROOM_BYTES
+// (bytes; 0 keeps the minimal ring), 8 GiB if unset.
+static size_t slot_room_bytes() {
+    const char* v = std::getenv("SWMI_SLOT_ROOM_BYTES");
+    if (!v || !*v) return (size_t)8 << 30;
+    return (size_t)std::strtoull(v, nullptr, 10);
+}
+
 EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>& specs, bool local,
                              int rows_per_lane, int waves_per_cu, int band_width) {
     EnginePlan p;
@@ -269,6 +278,11 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.n_probs, (int64_t)p.grid / 2));
     p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1 + (G > 1 ? 2 * G : 0));
     p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
+    // Where slots are small (many short problems), up to 8 GiB of them: tasks of
+    // different sizes finish out of ticket order, and a slot whose last reader is
+    // a long stripe would otherwise hold up the ticket that reuses it.
+    const int64_t roomy = (int64_t)(slot_room_bytes() / ((size_t)p.slot_stride * sizeof(int2)));
+    p.nslot = std::max(p.nslot, std::min<int64_t>(p.n_tickets, roomy));
     p.tickets.assign((size_t)p.n_tickets, Ticket{});
     std::vector<int32_t> tick_of((size_t)p.n_tasks, -1);  // task id (task0 + local) -> ticket, -1: none
     std::vector<int32_t> ntask((size_t)p.n_probs);         // tasks per problem (compact copy for the loops)

@@ -157,10 +157,12 @@ def test_tuning_is_used(ctx, orc):
         ctx.set_tuning(7, 8, 4)
 
 
-def test_batch_slot_reuse_across_problems(ctx, orc):
+def test_batch_slot_reuse_across_problems(ctx, orc, monkeypatch):
     """Regression: a slot is reused only after its previous owner finished writing it.  The last
     stripe of a problem has no reader, so the task after it can finish first; with few slots
-    (one wave per CU) and many multi-stripe pairs the reuse happens constantly."""
+    (one wave per CU, no slot room beyond the minimal ring) and many multi-stripe pairs the reuse
+    happens constantly."""
+    monkeypatch.setenv("SWMI_SLOT_ROOM_BYTES", "0")
     rng = np.random.default_rng(77)
     pairs = []
     for t in range(700):
