@@ -77,7 +77,7 @@ typedef struct {
     int32_t prune_mode;        /* sw_prune_mode */
     int32_t threshold;         /* > 0: use this T instead of the model's prediction (LEARNED mode) */
     const sw_model* model;     /* LEARNED mode: threshold model (sw_model_load) */
-    int32_t rows_per_lane;     /* 0 = the context's tuned value (else 8); else 4 or 8 */
+    int32_t rows_per_lane;     /* 0 = the context's tuned value (else 8); else 4, 6 or 8 */
     int32_t waves_per_cu;      /* 0 = the context's tuned value (else 8); else 1..16 stripe waves per CU */
     int32_t band_width;        /* 0 = automatic; else columns per band, a positive multiple of 64 */
     int32_t flags;             /* SW_FLAG_* bits */
@@ -132,7 +132,7 @@ sw_status sw_context_destroy(sw_context* ctx);
  * 1e10, below that BATCH when the launch holds more than one problem and
  * SMALL when it holds one.  Workspace sizes depend on
  * the shape: query them after changing the tuning.
- * rows_per_lane: 0 (untuned), 4 or 8; waves_per_cu: 0 (untuned) or 1..16. */
+ * rows_per_lane: 0 (untuned), 4, 6 or 8; waves_per_cu: 0 (untuned) or 1..16. */
 typedef enum {
     SW_TUNE_PAIR_SMALL = 0,
     SW_TUNE_PAIR_LARGE = 1,

@@ -24,9 +24,9 @@ import numpy as np
 
 from . import swmi
 
-# (rows per lane, waves per CU).  R = 8 runs a 256-VGPR build up to 8 waves per CU and a
-# 168-VGPR build (3 waves per SIMD) above; R = 4 a 128-VGPR build (up to 16 per CU).
-CANDIDATES = [(4, 8), (4, 12), (4, 16), (8, 4), (8, 6), (8, 8), (8, 10), (8, 12)]
+# (rows per lane, waves per CU).  R = 8 and R = 6 run a 256-VGPR build up to 8 waves per CU
+# and a 168-VGPR build (3 waves per SIMD) above; R = 4 a 128-VGPR build (up to 16 per CU).
+CANDIDATES = [(4, 8), (4, 12), (4, 16), (6, 12), (6, 16), (8, 4), (8, 6), (8, 8), (8, 10), (8, 12)]
 CACHE = os.environ.get("SWMI_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "swmi", "autotune.json"))
 

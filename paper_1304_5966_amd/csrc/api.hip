@@ -85,7 +85,7 @@ extern "C" sw_status sw_context_destroy(sw_context* ctx) {
 extern "C" sw_status sw_context_set_tuning(sw_context* ctx, int32_t cls, int32_t R, int32_t wpc) {
     if (!ctx) return fail(SW_EINVAL, "null context");
     if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
-    if (R != 0 && R != 4 && R != 8) return fail(SW_EINVAL, "rows_per_lane must be 0, 4 or 8 (got %d)", R);
+    if (R != 0 && R != 4 && R != 6 && R != 8) return fail(SW_EINVAL, "rows_per_lane must be 0, 4, 6 or 8 (got %d)", R);
     if (wpc < 0 || wpc > 16) return fail(SW_EINVAL, "waves_per_cu must be 0..16 (got %d)", wpc);
     ctx->tuned_R[cls] = R;
     ctx->tuned_wpc[cls] = wpc;
@@ -155,8 +155,8 @@ sw_status swmi::check_options(const sw_options* o) {
     if (!o) return SW_OK;
     if (o->prune_mode < SW_PRUNE_NONE || o->prune_mode > SW_PRUNE_LEARNED)
         return fail(SW_EINVAL, "unknown prune_mode %d", o->prune_mode);
-    if (o->rows_per_lane != 0 && o->rows_per_lane != 4 && o->rows_per_lane != 8)
-        return fail(SW_EINVAL, "rows_per_lane must be 0, 4 or 8 (got %d)", o->rows_per_lane);
+    if (o->rows_per_lane != 0 && o->rows_per_lane != 4 && o->rows_per_lane != 6 && o->rows_per_lane != 8)
+        return fail(SW_EINVAL, "rows_per_lane must be 0, 4, 6 or 8 (got %d)", o->rows_per_lane);
     if (o->waves_per_cu < 0 || o->waves_per_cu > 16)
         return fail(SW_EINVAL, "waves_per_cu must be 0..16 (got %d)", o->waves_per_cu);
     if (o->threshold < 0) return fail(SW_EINVAL, "threshold must be >= 0");

@@ -939,14 +939,16 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
 template <bool LOCAL, bool CD>
 static void launch_variant(const EngineArgs& args, int R, int occ, dim3 g, hipStream_t st) {
     const dim3 b(kWave);
-    if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4>), g, b, 0, st, args);
+    if (R == 6 && occ <= 2) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 2>), g, b, 0, st, args);
+    else if (R == 6) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 3>), g, b, 0, st, args);
+    else if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4>), g, b, 0, st, args);
     else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2>), g, b, 0, st, args);
     else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3>), g, b, 0, st, args);
 }
 
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st) {
-    if (rows_per_lane != 4 && rows_per_lane != 8) return hipErrorInvalidValue;
+    if (rows_per_lane != 4 && rows_per_lane != 6 && rows_per_lane != 8) return hipErrorInvalidValue;
     const int occ = (waves_per_cu + 3) / 4;  // waves per SIMD (4 SIMDs per CU)
     const dim3 g(grid);
     if (local && cd) launch_variant<true, true>(args, rows_per_lane, occ, g, st);

@@ -116,8 +116,8 @@ hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const 
                               hipStream_t st);
 // cd: run the fast ticks in the column-shifted domain (requires
 // match + gap_extend <= 127).
-// waves_per_cu picks the register budget: rows_per_lane 8 runs 2 waves per SIMD
-// (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
+// waves_per_cu picks the register budget: rows_per_lane 8 and 6 run 2 waves per
+// SIMD (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st);
 // rows_per_lane: the launch's R (records of tasks outside a kept band are skipped).

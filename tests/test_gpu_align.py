@@ -66,7 +66,7 @@ def test_align_small(ctx, orc, div):
         assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
 
 
-@pytest.mark.parametrize("R", [0, 8])
+@pytest.mark.parametrize("R", [0, 6, 8])
 @pytest.mark.parametrize("la,lb,div", [(3000, 2900, 0.05), (5200, 4100, 0.1), (2500, 6000, 0.15)])
 def test_align_gpu_levels(ctx, orc, la, lb, div, R):
     """Large enough that the top Myers-Miller levels run on the GPU; R = 0 lets the

@@ -31,7 +31,7 @@ def test_batch_mixed(ctx, orc):
         p = synth.homologous_pair(t, la, lb, 0.1) if (t % 2 and la and lb) else synth.random_pair(t, la, lb)
         pairs.append((p.a.tobytes(), p.b.tobytes()))
     for prune in (0, 1):
-        for R in (4, 8):
+        for R in (4, 6, 8):
             _case(f"batch mixed prune={prune} R={R}")
             got = ctx.batch(pairs, prune=prune, rows_per_lane=R)
             for (a, b), g in zip(pairs, got):
@@ -170,7 +170,7 @@ def test_batch_slot_reuse_across_problems(ctx, orc, monkeypatch):
         p = synth.homologous_pair(5000 + t, la, lb, 0.1) if t % 3 == 0 else synth.random_pair(5000 + t, la, lb)
         pairs.append((p.a.tobytes(), p.b.tobytes()))
     exp = [orc.sw_score(a, b) for a, b in pairs]
-    for R in (4, 8):
+    for R in (4, 6, 8):
         for rep in range(2):
             _case(f"slot reuse R={R} rep={rep}")
             got = ctx.batch(pairs, rows_per_lane=R, waves_per_cu=1)

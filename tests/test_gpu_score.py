@@ -32,7 +32,7 @@ def _case(msg):
 SIZES = [1, 2, 3, 63, 64, 65, 255, 256, 257, 511, 512, 513, 700, 1031]
 
 
-@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 12), (4, 16)])
+@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 12), (4, 16), (6, 12)])
 def test_random_shapes(ctx, orc, rows_per_lane, waves_per_cu):
     rng = np.random.default_rng(7 + rows_per_lane + waves_per_cu)
     for t in range(24):
@@ -47,7 +47,7 @@ def test_random_shapes(ctx, orc, rows_per_lane, waves_per_cu):
 
 
 @pytest.mark.parametrize("prune", [0, 1])
-@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 10)])
+@pytest.mark.parametrize("rows_per_lane,waves_per_cu", [(4, 0), (8, 0), (8, 10), (6, 8)])
 def test_homologous_multi_stripe(ctx, orc, prune, rows_per_lane, waves_per_cu):
     rng = np.random.default_rng(100 + prune + rows_per_lane)
     for la, lb in [(3000, 2900), (2100, 3300), (4100, 700), (900, 5000)]:
@@ -153,7 +153,7 @@ def test_config1_full(ctx, orc):
     p = synth.config1()
     a, b = p.a.tobytes(), p.b.tobytes()
     exp = orc.sw_score(a, b)
-    for R in (4, 8):
+    for R in (4, 6, 8):
         for prune in (0, 1):
             _case(f"config1 R={R} prune={prune}")
             assert ctx.score(a, b, rows_per_lane=R, prune=prune).key() == exp
