@@ -204,12 +204,14 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
         stripes += (s.M + rows_per_stripe - 1) / rows_per_stripe;
         maxN = std::max(maxN, s.N);
     }
-    // Band width: keep the slots (one per resident wave) within a fixed budget.
+    // Band width: keep the slot ring (sized as below) within a fixed budget.
     // Wide bands keep the stripe pipeline full: consecutive stripes run about
     // three ticks apart, so a band of T ticks keeps all waves busy only while
-    // grid * 3 <= T.  32 GiB (of 288 GB HBM) gives 2 Mi columns at 2048 waves.
+    // grid * 3 <= T.  32 GiB (of 288 GB HBM) gives 2 Mi columns at 2048 waves;
+    // on the 5 Mbp x 4 Mbp pair that budget (two bands) measured faster than
+    // 16, 24 or 64 GiB.
     const int64_t grid_est = std::max<int64_t>(1, std::min<int64_t>(max_grid, stripes * ((maxN + 63) / 64)));
-    const int64_t G_est = std::max<int64_t>(1, std::min<int64_t>((int64_t)specs.size(), grid_est / 2));
+    const int64_t G_est = std::max<int64_t>(1, std::min<int64_t>((int64_t)specs.size(), grid_est));
     const int64_t nslot_est = grid_est + 1 + (G_est > 1 ? 2 * G_est : 0);
     const size_t slot_budget = (size_t)32 << 30;
     int64_t Wg = (int64_t)(slot_budget / ((size_t)nslot_est * sizeof(int2))) - (kSlotPad + 2 * kTick);
