@@ -60,24 +60,22 @@ def profiled_traffic():
     return int(fields["traffic_bytes"])
 
 
-def cpu_baseline(pair, target_s=12.0):
-    """The oracle (single-threaded plain C) on a crop of the same pair around its planted piece."""
+def cpu_baseline(pair, target_s=15.0):
+    """The oracle (single-threaded plain C) on a crop of the same pair around its planted piece:
+    a short probe run sizes a square crop for about target_s seconds, which is then timed."""
     import oracle
     pl = pair.planted[0]
-    side = 40_000
-    a = pair.a[pl.a_off:pl.a_off + side].tobytes()
-    b = pair.b[pl.b_off:pl.b_off + side].tobytes()
-    t0 = time.perf_counter()
-    oracle.sw_score(a, b)
-    dt = time.perf_counter() - t0
-    if dt < target_s / 3:
-        side2 = int(side * (target_s / max(dt, 1e-3)) ** 0.5)
-        a = pair.a[pl.a_off:pl.a_off + side2].tobytes()
-        b = pair.b[pl.b_off:pl.b_off + side2].tobytes()
+
+    def timed(side):
+        a = pair.a[pl.a_off:pl.a_off + side].tobytes()
+        b = pair.b[pl.b_off:pl.b_off + side].tobytes()
         t0 = time.perf_counter()
         oracle.sw_score(a, b)
-        dt = time.perf_counter() - t0
-        side = side2
+        return a, b, time.perf_counter() - t0
+
+    _, _, dt = timed(20_000)
+    side = int(20_000 * (target_s / max(dt, 1e-3)) ** 0.5)
+    a, b, dt = timed(side)
     cells = len(a) * len(b)
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
             "sample": f"{len(a)} x {len(b)} crop of the same pair starting at its planted piece "
