@@ -327,6 +327,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
             tk.prod = q > 0 ? tof[l - 1] : -1;
             tk.left = band > 0 ? tof[l - pr.Q] : -1;
             tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tof[l - pr.Q - 1] : -1;
+            tk.cons = q + 1 < pr.Q ? tof[l + 1] : -1;
             if (q + 1 < pr.Q) reader[(size_t)j] = tof[l + 1];
         }
     }

@@ -527,6 +527,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         // to memory.  Both only grow: a value one tick old is a valid lower bound.
         const bool polls = q > 0 && prod_active;
         int32_t prod_pf = 0;
+        // Issue priority on the SIMD (local recurrence only): a stripe whose
+        // consumer is within a few ticks of its output, and so likely waiting
+        // for it, runs at a raised priority.  The chain's slowest link is then
+        // less often the younger wave of a shared SIMD.  A hint only: the
+        // consumer's count is never waited on.  The banded global passes keep
+        // plain arbitration (there the raised priority measured slower).
+        const bool has_cons = LOCAL && tkt.cons >= 0;
+        const int32_t* cons_prog = p.progress + (has_cons ? tkt.cons : 0);
+        int32_t cons_pf = 0;
         // The stripe's best recorded value and the first stripe row holding it
         // (wave-uniform; from exact row maxima only).
         int sb = LOCAL ? 0 : kNeg;
@@ -552,6 +561,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 b_next = reinterpret_cast<const uint32_t*>(
                     ((uintptr_t)(bcodes + c0 + (int64_t)kTick * (tau + 1) - (kTick - 1)) & ~(uintptr_t)3))[lane];
             if (polls && tau + 2 < n_ticks) prod_pf = load_count(prod_prog);
+            if (has_cons) cons_pf = load_count(cons_prog);
             const uint8_t* cols = bcodes + c0 + (int64_t)kTick * tau - lane;
 
             const int gb = gb_pf;
@@ -748,6 +758,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, o);
             }
             publish_count(p.progress + task, min(kTick * tau + 1, W));
+            if (has_cons) {
+                const int32_t cs = __builtin_amdgcn_readfirstlane(cons_pf);
+                if (cs > 0 && min(kTick * tau + 1, W) - cs <= 4 * kTick) __builtin_amdgcn_s_setprio(2);
+                else __builtin_amdgcn_s_setprio(0);
+            }
             if (!LOCAL && tau + 1 < n_ticks && !nxt_now) {
                 prod_seen = max(prod_seen, prod_pf);
                 nxt = fetch(kTick * (tau + 1), need_nxt);
@@ -786,6 +801,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             }
         }
         publish_count(p.progress + task, kDone);
+        __builtin_amdgcn_s_setprio(0);
     }
 }
 

@@ -66,7 +66,9 @@ struct Ticket {
     int32_t reuse_reader;  // reader of the slot this ticket reuses (ticket - nslot's consumer), -1 if none
     int32_t corner;        // without a producer task: ticket of the stripe above in the previous
                            // band, whose boundary capture holds this task's corner value; else -1
-    int32_t pad[2];
+    int32_t cons;          // ticket of the stripe below in the same band (-1: none); read only as
+                           // a scheduling hint, never waited on
+    int32_t pad;
 };
 
 // Does task (band, stripe q) of problem `pr` hold any cell of the kept
