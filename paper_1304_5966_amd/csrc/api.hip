@@ -381,6 +381,8 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
         const Ticket& t = plan.tickets[(size_t)k];
         if (t.prod >= k || t.left >= k || t.reuse_reader >= k || t.corner >= k)
             return fail(SW_EINTERNAL, "engine plan: ticket %lld waits on a younger ticket", (long long)k);
+        if (t.cons >= plan.n_tickets || (t.cons >= 0 && t.cons <= k))
+            return fail(SW_EINTERNAL, "engine plan: ticket %lld names consumer %d", (long long)k, t.cons);
     }
     EngineArgs a{};
     a.tickets = (const Ticket*)(base + plan.off_tickets);
