@@ -111,3 +111,53 @@ def test_config5_crop_alignment_properties(ctx, orc):
     for pl in inside:
         assert al.score >= orc.rescore(a, b, pl.a_off, pl.b_off, pl.transcript.cigar())[0]
     _check_windows(a, b, al, orc, np.random.default_rng(5))
+
+
+def test_config3_full_launch_sampled(ctx, orc):
+    """All 20 000 pairs of the batch workload in one launch, in the shape the benchmark's tuner
+    picks (6 rows per lane, 16 waves per CU): invariants on every pair, identical results under
+    running-best pruning and on graph replays, and the oracle on a seeded sample plus the
+    largest pairs."""
+    import torch
+    from paper_1304_5966_amd import swmi
+
+    _case("config3: generating 20 000 pairs")
+    pairs = synth.config3()
+    a = np.concatenate([p.a for p in pairs])
+    b = np.concatenate([p.b for p in pairs])
+    oa = np.concatenate(([0], np.cumsum([p.a.size for p in pairs]))).astype(np.int64)
+    ob = np.concatenate(([0], np.cumsum([p.b.size for p in pairs]))).astype(np.int64)
+    d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    shape = dict(rows_per_lane=6, waves_per_cu=16)
+
+    _case("config3: one launch, no pruning, R = 6 at 16 waves per CU")
+    keys = ctx.batch_dev(d_a, oa, d_b, ob, **shape).keys()
+    assert len(keys) == len(pairs)
+    for p, (s, ea, eb) in zip(pairs, keys):
+        la, lb = p.a.size, p.b.size
+        assert 0 <= s <= min(la, lb), p.tag  # match = +1
+        if s == 0:
+            assert (ea, eb) == (-1, -1), p.tag
+        else:
+            assert 0 <= ea < la and 0 <= eb < lb, p.tag
+
+    _case("config3: one launch, running-best pruning")
+    assert ctx.batch_dev(d_a, oa, d_b, ob, prune=swmi.PRUNE_BEST, **shape).keys() == keys
+
+    _case("config3: captured graph, two replays")
+    gstream = torch.cuda.Stream()
+    gctx = swmi.Context(0, stream=gstream)
+    try:
+        gws = torch.empty(gctx.batch_workspace_size(oa, ob, graph=True, **shape), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            assert gctx.batch_dev(d_a, oa, d_b, ob, workspace=gws, graph=True, **shape).keys() == keys
+    finally:
+        gctx.close()
+
+    cells = np.array([p.a.size * p.b.size for p in pairs])
+    rng = np.random.default_rng(20000)
+    idx = sorted(set(rng.choice(len(pairs), size=150, replace=False).tolist()) | set(np.argsort(cells)[-3:].tolist()))
+    _case(f"config3: oracle on {len(idx)} pairs of the launch")
+    for i in idx:
+        p = pairs[i]
+        assert keys[i] == orc.sw_score(p.a.tobytes(), p.b.tobytes()), p.tag
