@@ -44,7 +44,7 @@ def build(force: bool = False) -> str:
     """Compile gotoh.c into _liboracle.so with the host C compiler."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-pthread", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -64,9 +64,12 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, i64p, i64p, i64p]
             f.restype = ctypes.c_int
+        L.orc_sw_linear_mt.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int,
+                                       ctypes.c_int64, ctypes.c_int64, i64p, i64p, i64p]
+        L.orc_sw_start_mt.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_int64, i64p, i64p]
         L.orc_sw_matrix.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_void_p]
-        L.orc_sw_row_best.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp,
-                                      ctypes.c_void_p, ctypes.c_void_p]
         L.orc_sw_start.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int64,
                                    ctypes.c_int64, ctypes.c_int64, i64p, i64p]
         L.orc_mm_align.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, sp, ctypes.c_int64,
@@ -101,22 +104,45 @@ def sw_score(a, b, scoring=SCORING, full: bool = False):
     return int(s.value), int(ea.value), int(eb.value)
 
 
+def host_cores() -> int:
+    """Threads the multi-threaded modes use by default: the CPUs this process may run on,
+    at most 16 (the host share of one GPU on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def sw_score_mt(a, b, scoring=SCORING, threads: int = 0, stripe_rows: int = 0, chunk_cols: int = 0):
+    """sw_score in linear space over row stripes on several threads (same result)."""
+    a, b = _bytes(a), _bytes(b)
+    s, ea, eb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().orc_sw_linear_mt(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), threads or host_cores(),
+                                stripe_rows, chunk_cols, ctypes.byref(s), ctypes.byref(ea), ctypes.byref(eb))
+    if rc:
+        raise ValueError("oracle: invalid arguments or out of memory")
+    return int(s.value), int(ea.value), int(eb.value)
+
+
+def sw_start_mt(a, b, score, end_a, end_b, scoring=SCORING, threads: int = 0, stripe_rows: int = 0,
+                chunk_cols: int = 0):
+    """sw_start over row stripes on several threads (same result)."""
+    a, b = _bytes(a), _bytes(b)
+    sa, sb = ctypes.c_int64(), ctypes.c_int64()
+    if lib().orc_sw_start_mt(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), score, end_a, end_b,
+                             threads or host_cores(), stripe_rows, chunk_cols, ctypes.byref(sa),
+                             ctypes.byref(sb)):
+        raise ValueError("oracle: start not found / invalid arguments")
+    return int(sa.value), int(sb.value)
+
+
 def sw_matrix(a, b, scoring=SCORING) -> np.ndarray:
     a, b = _bytes(a), _bytes(b)
     H = np.zeros((len(a) + 1, len(b) + 1), dtype=np.int64)
     if lib().orc_sw_matrix(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), H.ctypes.data):
         raise ValueError("oracle: invalid arguments")
     return H
-
-
-def sw_row_best(a, b, scoring=SCORING):
-    a, b = _bytes(a), _bytes(b)
-    rb = np.zeros(len(a), dtype=np.int64)
-    rc = np.zeros(len(a), dtype=np.int64)
-    if lib().orc_sw_row_best(a, len(a), b, len(b), ctypes.byref(_sc(scoring)), rb.ctypes.data,
-                             rc.ctypes.data):
-        raise ValueError("oracle: invalid arguments")
-    return rb, rc
 
 
 def sw_start(a, b, score, end_a, end_b, scoring=SCORING):

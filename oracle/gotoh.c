@@ -23,6 +23,9 @@
  *    zero and with minus-infinity borders except the anchor, run on the reversed
  *    prefixes that end at the endpoint; the start is the lexicographically
  *    smallest reversed cell whose value equals S.
+ *  - the same two passes over row stripes on several threads (Section 2,
+ *    linear memory), for inputs too large for one core: orc_sw_linear_mt and
+ *    orc_sw_start_mt; cells are computed by the same formulas.
  *  - alignment (Section 2, reconstruction phase): Myers-Miller divide and
  *    conquer on the start..end rectangle with gap cost g + h*k, g = open -
  *    extend, h = extend; midline ties go to the smallest column, a plain
@@ -30,6 +33,9 @@
  *
  * Every function returns 0 on success, -1 on invalid arguments.
  */
+#include <pthread.h>
+#include <sched.h>
+#include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -141,28 +147,203 @@ int orc_sw_linear(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, cons
     return 0;
 }
 
-/* Best local score of every row of the matrix (property tests: pruning bounds, sampling). */
-int orc_sw_row_best(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
-                    int64_t* row_best, int64_t* row_col) {
-    if (bad_args(a, m, b, n, sc)) return -1;
-    int64_t* H = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
-    int64_t* F = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
-    if (!H || !F) { free(H); free(F); return -1; }
-    for (int64_t j = 0; j <= n; j++) { H[j] = 0; F[j] = ORC_NEG; }
-    for (int64_t i = 1; i <= m; i++) {
-        int64_t diag = H[0], e = ORC_NEG, rb = 0, rc = -1;
-        H[0] = 0;
-        for (int64_t j = 1; j <= n; j++) {
-            e = max2(e - sc->gap_extend, H[j - 1] - sc->gap_open);
-            F[j] = max2(F[j] - sc->gap_extend, H[j] - sc->gap_open);
-            int64_t h = max2(max2(diag + sub_score(a[i - 1], b[j - 1], sc), 0), max2(e, F[j]));
-            diag = H[j];
-            H[j] = h;
-            if (h > rb) { rb = h; rc = j - 1; }
-        }
-        row_best[i - 1] = rb; row_col[i - 1] = rc;
+/* ------------------------------------------------------------------ linear space, several threads */
+
+/*
+ * The row-by-row recurrence above, spread over threads as a pipeline of row
+ * stripes (stripe s holds rows s*h+1 .. s*h+h).  Thread t runs stripes t,
+ * t + T, t + 2T, ... in that order.  A stripe walks the columns in chunks; it
+ * starts a chunk once the stripe above has published its bottom row (H and F)
+ * up to the chunk's last column.  Bottom rows go to a ring of K row buffers;
+ * before writing buffer s mod K a stripe waits until the stripe that read the
+ * buffer's previous contents (stripe s - K + 1) has finished.  A stripe only
+ * ever waits on older stripes, so the oldest unfinished one always runs.
+ *
+ * Every cell is computed by the formulas of orc_sw_linear (or, anchored, of
+ * orc_sw_start); the order in which cells are visited changes, so the cell
+ * holding the answer is chosen by comparing (row, column) explicitly.
+ *
+ *   local    (orc_sw_linear_mt): zero borders and floor; S = max H, the
+ *            endpoint is the lexicographically smallest cell holding S.
+ *   anchored (orc_sw_start_mt):  orc_sw_start's reverse pass on reversed
+ *            copies of the prefixes; the start is the lexicographically
+ *            smallest reversed cell holding S.
+ */
+typedef struct {
+    const uint8_t *a, *b;
+    int64_t m, n;
+    const orc_scoring* sc;
+    int anchored;          /* 0: local; 1: anchored global recurrence */
+    int64_t target;        /* anchored: the value searched for */
+    int64_t h, chunk;      /* rows per stripe, columns per chunk */
+    int64_t nstripes, K;
+    int T;
+    int64_t* ringH;        /* K rows of n + 1 values each */
+    int64_t* ringF;
+    _Atomic int64_t* progress;  /* per stripe: last column of its bottom row published */
+    int64_t *rbest, *ri, *rj;   /* per stripe: best value (local) and its cell; anchored: first hit */
+    int failed;
+} mt_job;
+
+typedef struct {
+    mt_job* J;
+    int t;
+} mt_arg;
+
+static void mt_wait(_Atomic int64_t* p, int64_t need) {
+    while (atomic_load_explicit(p, memory_order_acquire) < need) sched_yield();
+}
+
+/* (i1, j1) before (i2, j2) in row-major order */
+static int lex_less(int64_t i1, int64_t j1, int64_t i2, int64_t j2) {
+    return i1 < i2 || (i1 == i2 && j1 < j2);
+}
+
+/* Row 0 of the matrix. */
+static int64_t mt_top(const mt_job* J, int64_t j) {
+    if (!J->anchored) return 0;
+    return j == 0 ? 0 : ORC_NEG;
+}
+
+static void mt_stripe(mt_job* J, int64_t s, int64_t* Hc, int64_t* Fc, int64_t* Hl, int64_t* El) {
+    const int64_t n = J->n, r0 = s * J->h;
+    const int64_t r1 = r0 + J->h < J->m ? r0 + J->h : J->m;
+    const orc_scoring* sc = J->sc;
+    const int64_t ext = sc->gap_extend, open = sc->gap_open;
+    const uint8_t *A = J->a, *B = J->b;
+    const int anchored = J->anchored;
+    const int64_t target = J->target;
+    if (s >= J->K) mt_wait(&J->progress[s - J->K + 1], n);
+    const int64_t* upH = s > 0 ? J->ringH + ((s - 1) % J->K) * (n + 1) : NULL;
+    const int64_t* upF = s > 0 ? J->ringF + ((s - 1) % J->K) * (n + 1) : NULL;
+    int64_t* outH = J->ringH + (s % J->K) * (n + 1);
+    int64_t* outF = J->ringF + (s % J->K) * (n + 1);
+    for (int64_t k = 0; k < r1 - r0; k++) {
+        Hl[k] = J->anchored ? ORC_NEG : 0;  /* H(i, 0), i >= 1 */
+        El[k] = ORC_NEG;                    /* E(i, 0) */
     }
-    free(H); free(F);
+    int64_t best = 0, bi = INT64_MAX, bj = INT64_MAX;
+    for (int64_t c0 = 1; c0 <= n; c0 += J->chunk) {
+        const int64_t c1 = c0 + J->chunk - 1 < n ? c0 + J->chunk - 1 : n;
+        if (s > 0) mt_wait(&J->progress[s - 1], c1);
+        /* the row above the stripe over columns c0-1 .. c1, at index j - (c0 - 1) */
+        for (int64_t j = c0 - 1; j <= c1; j++) {
+            Hc[j - c0 + 1] = s > 0 ? upH[j] : mt_top(J, j);
+            Fc[j - c0 + 1] = s > 0 ? upF[j] : ORC_NEG;
+        }
+        for (int64_t k = 0; k < r1 - r0; k++) {
+            const int64_t i = r0 + k + 1;
+            const uint8_t ai = A[i - 1];
+            int64_t diag = Hc[0];  /* H(i-1, c0-1) */
+            int64_t e = El[k];     /* E(i, c0-1) */
+            Hc[0] = Hl[k];         /* H(i, c0-1) */
+            for (int64_t j = c0; j <= c1; j++) {
+                const int64_t x = j - c0 + 1;
+                e = max2(e - ext, Hc[x - 1] - open);       /* Hc[x-1] = H(i, j-1) */
+                Fc[x] = max2(Fc[x] - ext, Hc[x] - open);   /* Hc[x]   = H(i-1, j) */
+                int64_t hv = max2(diag + sub_score(ai, B[j - 1], sc), max2(e, Fc[x]));
+                if (!anchored) hv = max2(hv, 0);
+                diag = Hc[x];
+                Hc[x] = hv;
+                if (anchored) {
+                    if (hv == target && lex_less(i - 1, j - 1, bi, bj)) { bi = i - 1; bj = j - 1; }
+                } else if (hv > 0 && (hv > best || (hv == best && lex_less(i - 1, j - 1, bi, bj)))) {
+                    best = hv; bi = i - 1; bj = j - 1;
+                }
+            }
+            Hl[k] = Hc[c1 - c0 + 1];
+            El[k] = e;
+        }
+        /* Hc, Fc now hold the stripe's bottom row */
+        if (c0 == 1) { outH[0] = J->anchored ? ORC_NEG : 0; outF[0] = ORC_NEG; }
+        for (int64_t j = c0; j <= c1; j++) { outH[j] = Hc[j - c0 + 1]; outF[j] = Fc[j - c0 + 1]; }
+        atomic_store_explicit(&J->progress[s], c1, memory_order_release);
+    }
+    J->rbest[s] = best;
+    J->ri[s] = bi;
+    J->rj[s] = bj;
+}
+
+static void* mt_thread(void* p) {
+    mt_arg* A = (mt_arg*)p;
+    mt_job* J = A->J;
+    int64_t* Hc = (int64_t*)malloc((size_t)(J->chunk + 1) * sizeof(int64_t));
+    int64_t* Fc = (int64_t*)malloc((size_t)(J->chunk + 1) * sizeof(int64_t));
+    int64_t* Hl = (int64_t*)malloc((size_t)J->h * sizeof(int64_t));
+    int64_t* El = (int64_t*)malloc((size_t)J->h * sizeof(int64_t));
+    if (!Hc || !Fc || !Hl || !El) {
+        /* cannot run: abort the whole job (every waiter sees a finished stripe) */
+        J->failed = 1;
+        for (int64_t s = A->t; s < J->nstripes; s += J->T) atomic_store(&J->progress[s], J->n);
+    } else {
+        for (int64_t s = A->t; s < J->nstripes; s += J->T) mt_stripe(J, s, Hc, Fc, Hl, El);
+    }
+    free(Hc); free(Fc); free(Hl); free(El);
+    return NULL;
+}
+
+/* Runs the job on J->T threads; per-stripe results in rbest / ri / rj. */
+static int mt_run(mt_job* J) {
+    J->nstripes = (J->m + J->h - 1) / J->h;
+    J->K = 2 * (int64_t)J->T;
+    if (J->K < 2) J->K = 2;
+    J->failed = 0;
+    const size_t row = (size_t)(J->n + 1);
+    J->ringH = (int64_t*)malloc((size_t)J->K * row * sizeof(int64_t));
+    J->ringF = (int64_t*)malloc((size_t)J->K * row * sizeof(int64_t));
+    J->progress = (_Atomic int64_t*)malloc((size_t)J->nstripes * sizeof(_Atomic int64_t));
+    J->rbest = (int64_t*)malloc((size_t)J->nstripes * sizeof(int64_t));
+    J->ri = (int64_t*)malloc((size_t)J->nstripes * sizeof(int64_t));
+    J->rj = (int64_t*)malloc((size_t)J->nstripes * sizeof(int64_t));
+    pthread_t* th = (pthread_t*)malloc((size_t)J->T * sizeof(pthread_t));
+    mt_arg* args = (mt_arg*)malloc((size_t)J->T * sizeof(mt_arg));
+    int rc = -1;
+    if (J->ringH && J->ringF && J->progress && J->rbest && J->ri && J->rj && th && args) {
+        for (int64_t s = 0; s < J->nstripes; s++) atomic_init(&J->progress[s], 0);
+        int started = 0;
+        for (int t = 0; t < J->T; t++) {
+            args[t].J = J;
+            args[t].t = t;
+            if (pthread_create(&th[t], NULL, mt_thread, &args[t]) != 0) break;
+            started++;
+        }
+        if (started < J->T) {
+            /* the stripes of threads that did not start are marked finished so that
+             * no waiter blocks; the job reports failure */
+            J->failed = 1;
+            for (int t = started; t < J->T; t++)
+                for (int64_t s = t; s < J->nstripes; s += J->T) atomic_store(&J->progress[s], J->n);
+        }
+        for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+        rc = J->failed ? -1 : 0;
+    }
+    free(J->ringH); free(J->ringF); free((void*)J->progress); free(th); free(args);
+    if (rc) { free(J->rbest); free(J->ri); free(J->rj); }
+    return rc;
+}
+
+/* orc_sw_linear on `threads` threads; stripe_rows / chunk_cols 0 = 512 / 16384. */
+int orc_sw_linear_mt(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                     int threads, int64_t stripe_rows, int64_t chunk_cols,
+                     int64_t* score, int64_t* end_a, int64_t* end_b) {
+    if (bad_args(a, m, b, n, sc) || threads < 1 || stripe_rows < 0 || chunk_cols < 0) return -1;
+    *score = 0; *end_a = -1; *end_b = -1;
+    if (m == 0 || n == 0) return 0;
+    mt_job J;
+    memset(&J, 0, sizeof J);
+    J.a = a; J.b = b; J.m = m; J.n = n; J.sc = sc;
+    J.anchored = 0;
+    J.h = stripe_rows ? stripe_rows : 512;
+    J.chunk = chunk_cols ? chunk_cols : 16384;
+    J.T = threads;
+    if (mt_run(&J)) return -1;
+    int64_t best = 0, bi = INT64_MAX, bj = INT64_MAX;
+    for (int64_t s = 0; s < J.nstripes; s++)
+        if (J.rbest[s] > 0 && (J.rbest[s] > best || (J.rbest[s] == best && lex_less(J.ri[s], J.rj[s], bi, bj)))) {
+            best = J.rbest[s]; bi = J.ri[s]; bj = J.rj[s];
+        }
+    free(J.rbest); free(J.ri); free(J.rj);
+    if (best > 0) { *score = best; *end_a = bi; *end_b = bj; }
     return 0;
 }
 
@@ -206,6 +387,40 @@ int orc_sw_start(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const
     }
     free(H); free(F);
     return found ? 0 : -1;
+}
+
+/* orc_sw_start on `threads` threads (same result; stripe_rows / chunk_cols as above). */
+int orc_sw_start_mt(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc,
+                    int64_t score, int64_t end_a, int64_t end_b, int threads, int64_t stripe_rows,
+                    int64_t chunk_cols, int64_t* start_a, int64_t* start_b) {
+    if (bad_args(a, m, b, n, sc) || threads < 1 || stripe_rows < 0 || chunk_cols < 0) return -1;
+    if (score <= 0) { *start_a = -1; *start_b = -1; return 0; }
+    if (end_a < 0 || end_a >= m || end_b < 0 || end_b >= n) return -1;
+    const int64_t rm = end_a + 1, rn = end_b + 1;
+    uint8_t* ra = (uint8_t*)malloc((size_t)rm);
+    uint8_t* rb = (uint8_t*)malloc((size_t)rn);
+    if (!ra || !rb) { free(ra); free(rb); return -1; }
+    for (int64_t i = 0; i < rm; i++) ra[i] = a[end_a - i];
+    for (int64_t j = 0; j < rn; j++) rb[j] = b[end_b - j];
+    mt_job J;
+    memset(&J, 0, sizeof J);
+    J.a = ra; J.b = rb; J.m = rm; J.n = rn; J.sc = sc;
+    J.anchored = 1;
+    J.target = score;
+    J.h = stripe_rows ? stripe_rows : 512;
+    J.chunk = chunk_cols ? chunk_cols : 16384;
+    J.T = threads;
+    int rc = mt_run(&J);
+    free(ra); free(rb);
+    if (rc) return -1;
+    int64_t bi = INT64_MAX, bj = INT64_MAX;
+    for (int64_t s = 0; s < J.nstripes; s++)
+        if (lex_less(J.ri[s], J.rj[s], bi, bj)) { bi = J.ri[s]; bj = J.rj[s]; }
+    free(J.rbest); free(J.ri); free(J.rj);
+    if (bi == INT64_MAX) return -1;
+    *start_a = end_a - bi;
+    *start_b = end_b - bj;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ Myers-Miller */

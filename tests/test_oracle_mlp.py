@@ -1,8 +1,9 @@
 """Pins of the CPU references for the learned threshold (oracle/mlp.py).
 
 The feature extractor is pinned by hand-derivable cases (identical sequences,
-a single planted diagonal, bin boundaries) and invariants; the float64
-backward pass is pinned by central finite differences.
+planted runs on known diagonals grouped into 64-diagonal bands, the 64-copy
+repeat cap, bin boundaries) and invariants; the float64 backward pass is
+pinned by central finite differences.
 """
 import numpy as np
 import pytest
@@ -98,3 +99,69 @@ def test_pinball_loss_pins():
     assert 0.0 <= best <= 1.0  # any point of [t(1), t(2)] minimises at q = 0.2 with five targets
     np.testing.assert_array_equal(mlp.loss_grad(np.array([0.0, 1.0, 2.0]), np.array([1.0, 1.0, 1.0]), 0.3),
                                   np.array([-0.3, 0.0, 0.7]) / 3)
+
+
+def _hist(x):
+    return np.round(np.expm1(x[128:254])).astype(int)
+
+
+def _runs_pair(rng, runs, la=2600):
+    """A: poly-A filler holding random pieces at given offsets; B: poly-C filler holding the same
+    pieces at given offsets.  Filler 12-mers never hit (poly-A occurs far more than 64 times in
+    A and is dropped; poly-C does not occur in A), so the only hits are the pieces' own 12-mers,
+    each run on the single diagonal j - i of its copy."""
+    a = bytearray(b"A" * la)
+    lb = max(jb + len(p) for _, jb, p in runs) + 300
+    b = bytearray(b"C" * lb)
+    for ia, jb, piece in runs:
+        a[ia:ia + len(piece)] = piece
+        b[jb:jb + len(piece)] = piece
+    return bytes(a), bytes(b)
+
+
+def _piece(rng, n):
+    while True:
+        p = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), n).tobytes()
+        if b"AAAAAA" not in p and b"CCCCCC" not in p:
+            return p
+
+
+def test_planted_diagonals_land_in_their_band():
+    """Two planted runs whose diagonals d1, d2 satisfy (d + |A|) // 64 equal: one band holding both
+    counts; shifted so that they straddle a band edge: two bands.  A wrong band width, sign or
+    offset groups them differently."""
+    rng = np.random.default_rng(5)
+    p1, p2 = _piece(rng, 100), _piece(rng, 150)   # 89 and 139 twelve-mer hits
+    la = 2600
+    i1, i2 = 500, 1500
+    # same band: (d + la) % 64 = 10 and 50 with equal (d + la) // 64
+    base = 64 * ((la + 300) // 64)              # a multiple of 64 above la
+    d1, d2 = base + 10 - la, base + 50 - la
+    a, b = _runs_pair(rng, [(i1, i1 + d1, p1), (i2, i2 + d2, p2)], la)
+    h = _hist(mlp.features(a, b))
+    n_bands = (len(a) + len(b)) // 64 + 2
+    assert h[mlp.log_bin(89 + 139)] == 1
+    assert h[0] == n_bands - 1
+    # straddling: (d + la) % 64 = 60 and 4 of the next band
+    d1, d2 = base + 60 - la, base + 68 - la
+    a, b = _runs_pair(rng, [(i1, i1 + d1, p1), (i2, i2 + d2, p2)], la)
+    h = _hist(mlp.features(a, b))
+    n_bands = (len(a) + len(b)) // 64 + 2
+    assert h[mlp.log_bin(89)] == 1 and h[mlp.log_bin(139)] == 1
+    assert h[0] == n_bands - 2
+
+
+@pytest.mark.parametrize("copies,kept", [(64, True), (65, False)])
+def test_repeat_cap(copies, kept):
+    """A 12-mer occurring 64 times in A keeps its hits; at 65 occurrences all are dropped.  The
+    copies sit 76 apart (a 64-letter poly-T spacer), so each hit falls in a band of its own."""
+    k = b"ACGTTACGATCA"
+    a = (k + b"T" * 64) * copies
+    b = b"G" * 50 + k + b"G" * 50
+    h = _hist(mlp.features(a, b))
+    n_bands = (len(a) + len(b)) // 64 + 2
+    if kept:
+        assert h[mlp.log_bin(1)] == copies
+        assert h[0] == n_bands - copies
+    else:
+        assert h[0] == n_bands
