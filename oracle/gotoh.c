@@ -182,6 +182,7 @@ typedef struct {
     int64_t* ringF;
     _Atomic int64_t* progress;  /* per stripe: last column of its bottom row published */
     int64_t *rbest, *ri, *rj;   /* per stripe: best value (local) and its cell; anchored: first hit */
+    _Atomic int64_t hit_stripe; /* anchored: lowest stripe known to hold a cell equal to the target */
     int failed;
 } mt_job;
 
@@ -226,6 +227,15 @@ static void mt_stripe(mt_job* J, int64_t s, int64_t* Hc, int64_t* Fc, int64_t* H
     for (int64_t c0 = 1; c0 <= n; c0 += J->chunk) {
         const int64_t c1 = c0 + J->chunk - 1 < n ? c0 + J->chunk - 1 : n;
         if (s > 0) mt_wait(&J->progress[s - 1], c1);
+        if (anchored && atomic_load_explicit(&J->hit_stripe, memory_order_acquire) < s) {
+            /* An earlier stripe holds a hit: every row here comes after it, so no cell of this
+             * stripe can be the first one (the single-threaded pass stops at that row too).
+             * Later stripes see the same hit and stop as well, so the partly written bottom
+             * row is never read. */
+            J->rbest[s] = 0; J->ri[s] = INT64_MAX; J->rj[s] = INT64_MAX;
+            atomic_store_explicit(&J->progress[s], n, memory_order_release);
+            return;
+        }
         /* the row above the stripe over columns c0-1 .. c1, at index j - (c0 - 1) */
         for (int64_t j = c0 - 1; j <= c1; j++) {
             Hc[j - c0 + 1] = s > 0 ? upH[j] : mt_top(J, j);
@@ -262,6 +272,11 @@ static void mt_stripe(mt_job* J, int64_t s, int64_t* Hc, int64_t* Fc, int64_t* H
     J->rbest[s] = best;
     J->ri[s] = bi;
     J->rj[s] = bj;
+    if (anchored && bi != INT64_MAX) {
+        int64_t cur = atomic_load(&J->hit_stripe);
+        while (s < cur && !atomic_compare_exchange_weak(&J->hit_stripe, &cur, s)) {
+        }
+    }
 }
 
 static void* mt_thread(void* p) {
@@ -300,6 +315,7 @@ static int mt_run(mt_job* J) {
     int rc = -1;
     if (J->ringH && J->ringF && J->progress && J->rbest && J->ri && J->rj && th && args) {
         for (int64_t s = 0; s < J->nstripes; s++) atomic_init(&J->progress[s], 0);
+        atomic_init(&J->hit_stripe, INT64_MAX);
         int started = 0;
         for (int t = 0; t < J->T; t++) {
             args[t].J = J;
