@@ -18,7 +18,7 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-def test_traffic_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
+def test_counters_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
     src_dir = tmp_path / "paper_1304_5966_amd" / "csrc"
     src_dir.mkdir(parents=True)
     (tmp_path / "profiles").mkdir()
@@ -26,9 +26,17 @@ def test_traffic_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
     src.write_bytes(b"// kernel v1\n")
     sha = hashlib.sha256(b"// kernel v1\n").hexdigest()[:16]
     (tmp_path / "profiles" / "engine_kernel_5Mx4M_counters.md").write_text(
-        f"# counters\n\nengine_hip_sha256_prefix: {sha}\ntraffic_bytes: 123456\n")
+        f"# counters\n\nengine_hip_sha256_prefix: {sha}\ntraffic_bytes: 123456\n"
+        f"sq_insts_valu: 2.5e11\ncells: 2.0e12\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.profiled_traffic() == 123456
+    c = bench.profiled_counters()
+    assert c == {"match": True, "traffic": 123456, "valu_per_cell": 8.0}
+    r = bench.roofline(2.0e12, 1.0, c)
+    # 2.5e11 wave instructions x 64 lanes / 2e12 cells = 8 lane-instructions per cell; 8 x 2e12 in 1 s
+    assert r["achieved"] == 16.0 and r["frac"] == round(16e12 / bench.VALU_PEAK, 4)
+    assert r["traffic"] == 123456 and r["valu_per_cell"] == 8.0
+    assert r["algorithmic_tops"] == 20.0  # 10 operations per cell
     src.write_bytes(b"// kernel v2\n")  # source changed since the counters were taken
-    assert bench.profiled_traffic() is None
-
+    c = bench.profiled_counters()
+    assert c["match"] is False
+    assert bench.roofline(2.0e12, 1.0, c)["traffic"] is None
