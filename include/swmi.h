@@ -158,6 +158,21 @@ sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const
                        int64_t len_b, const sw_scoring* scoring, const sw_options* options,
                        void* d_workspace, size_t workspace_bytes, sw_score_result* out);
 
+/* sw_score_dev without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Every intermediate lives in a fixed
+ * scratch array of SW_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device it runs on until the process ends; the call allocates nothing.  A
+ * pair whose workspace (sw_score_workspace_size with the same options)
+ * exceeds the scratch fails with SW_ENOMEM before any device work.  All calls
+ * on one device share that device's scratch and clear what they read before
+ * writing it: calls that overlap in time on one device (two streams, two
+ * threads) race and must not be issued. */
+#define SW_NOALLOC_SCRATCH_BYTES (256ull << 20)
+sw_status sw_score_dev_noalloc(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const uint8_t* d_b,
+                               int64_t len_b, const sw_scoring* scoring, const sw_options* options,
+                               sw_score_result* out);
+
 /* All three phases (paper Section 2): score, start, end and the canonical
  * CIGAR.  out->cigar is allocated by the library; release it with
  * sw_align_result_free. */

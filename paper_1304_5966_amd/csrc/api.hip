@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -41,6 +42,33 @@ extern "C" const char* sw_version(void) { return "swmi 0.2 (gfx950)"; }
 
 size_t swmi::align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// ------------------------------------------------------------------------ fixed scratch
+
+// Workspace of sw_score_dev_noalloc: one fixed device array per GPU, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not the
+// device memory; the device address comes from hipGetSymbolAddress, once per
+// device (scratch_address), and only that address is ever passed to kernels or
+// copies.
+static __device__ __align__(256) uint8_t scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];  // device address of `scratch` per device ordinal
+
+// Device address of the scratch array on `device`, which must be current.
+static sw_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= 64) return fail(SW_EUNSUPPORTED, "device ordinal %d above 63", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SW_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return SW_OK;
+}
+
 // ------------------------------------------------------------------------ context
 
 extern "C" sw_status sw_context_create(int device, void* hip_stream, sw_context** out) {
@@ -60,6 +88,11 @@ extern "C" sw_status sw_context_create(int device, void* hip_stream, sw_context*
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->num_cu = prop.multiProcessorCount;
+    sw_status sst = scratch_address(device, &c->scratch);
+    if (sst != SW_OK) {
+        delete c;
+        return sst;
+    }
     c->host_misc_bytes = (size_t)64 << 10;
     hipError_t e = hipHostMalloc((void**)&c->host_misc, c->host_misc_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -553,6 +586,30 @@ extern "C" sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t l
     if (!d_workspace) return fail(SW_EINVAL, "sw_score_dev: NULL workspace");
     HIP_TRY(hipSetDevice(ctx->device));
     return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, d_workspace, workspace_bytes, out);
+}
+
+extern "C" sw_status sw_score_dev_noalloc(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const uint8_t* d_b,
+                                          int64_t len_b, const sw_scoring* scoring, const sw_options* options,
+                                          sw_score_result* out) {
+    if (!ctx || !out) return fail(SW_EINVAL, "sw_score_dev_noalloc: NULL context or result");
+    sw_status st;
+    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    if ((st = check_options(options)) != SW_OK) return st;
+    if ((len_a && !d_a) || (len_b && !d_b)) return fail(SW_EINVAL, "sw_score_dev_noalloc: NULL sequence pointer");
+    if (len_a == 0 || len_b == 0) {
+        std::memset(out, 0, sizeof *out);
+        out->end_a = out->end_b = -1;
+        return SW_OK;
+    }
+    const size_t need = score_workspace_size(ctx, len_a, len_b, options);
+    if (need > (size_t)SW_NOALLOC_SCRATCH_BYTES)
+        return fail(SW_ENOMEM, "sw_score_dev_noalloc: the pair needs %zu bytes of workspace, the fixed scratch "
+                    "holds %zu (use sw_score_dev with a caller workspace)", need, (size_t)SW_NOALLOC_SCRATCH_BYTES);
+    HIP_TRY(hipSetDevice(ctx->device));
+    // Every intermediate the pass reads before writing (encode flags, counters,
+    // running bests, records) is cleared by kernels inside run_score.
+    return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, ctx->scratch, SW_NOALLOC_SCRATCH_BYTES, out);
 }
 
 // Uploads host letters into the context's input buffer (checked on the device).

@@ -76,6 +76,8 @@ def _load():
     L.sw_score_workspace_size.restype = ctypes.c_size_t
     L.sw_score_dev.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(Scoring), ctypes.POINTER(Options),
                                vp, ctypes.c_size_t, ctypes.POINTER(ScoreResult)]
+    L.sw_score_dev_noalloc.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(Scoring), ctypes.POINTER(Options),
+                                       ctypes.POINTER(ScoreResult)]
     L.sw_align.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring),
                            ctypes.POINTER(Options), ctypes.POINTER(AlignResult)]
     L.sw_align_result_free.argtypes = [ctypes.POINTER(AlignResult)]
@@ -106,7 +108,7 @@ def _load():
     L.sw_mlp_adam_dev.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, vp]
     for name in ("sw_context_create", "sw_context_destroy", "sw_context_set_tuning",
-                 "sw_context_get_tuning", "sw_score", "sw_score_dev", "sw_align",
+                 "sw_context_get_tuning", "sw_score", "sw_score_dev", "sw_score_dev_noalloc", "sw_align",
                  "sw_start", "sw_batch", "sw_batch_dev", "sw_mm_host", "sw_model_load", "sw_model_free",
                  "sw_features_dev", "sw_mlp_standardize_dev", "sw_mlp_forward_dev", "sw_mlp_backward_dev",
                  "sw_mlp_adam_dev"):
@@ -118,7 +120,8 @@ lib = _load()
 
 EXPORTED = ("sw_last_error", "sw_version", "sw_context_create", "sw_context_destroy",
             "sw_context_set_tuning", "sw_context_get_tuning", "sw_score",
-            "sw_score_workspace_size", "sw_score_dev", "sw_align", "sw_align_result_free", "sw_start",
+            "sw_score_workspace_size", "sw_score_dev", "sw_score_dev_noalloc", "sw_align",
+            "sw_align_result_free", "sw_start",
             "sw_batch", "sw_batch_workspace_size", "sw_batch_dev", "sw_mm_host", "sw_model_load",
             "sw_model_free", "sw_mlp_param_count", "sw_features_workspace_size", "sw_features_dev",
             "sw_mlp_standardize_dev", "sw_mlp_forward_dev", "sw_mlp_backward_dev", "sw_mlp_adam_dev")
@@ -332,6 +335,19 @@ class Context:
                                 ctypes.byref(_options(**opts)), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), ctypes.byref(r)))
         return _score_of(r)
+
+
+    def score_dev_noalloc(self, d_a, d_b, scoring=DEFAULT_SCORING, **opts) -> Score:
+        """score_dev with the library's fixed scratch as workspace (no allocation anywhere)."""
+        r = ScoreResult()
+        _check(lib.sw_score_dev_noalloc(self.handle, ctypes.c_void_p(d_a.data_ptr()), int(d_a.numel()),
+                                        ctypes.c_void_p(d_b.data_ptr()), int(d_b.numel()),
+                                        ctypes.byref(Scoring(*scoring)), ctypes.byref(_options(**opts)),
+                                        ctypes.byref(r)))
+        return _score_of(r)
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20  # SW_NOALLOC_SCRATCH_BYTES
 
 
 def _ptr(t):
