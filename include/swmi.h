@@ -73,6 +73,10 @@ typedef enum {
 
 typedef struct sw_model sw_model;
 
+/* Progress of a long score pass: called on the calling thread after each row
+ * slab with the rows of A done so far and the total. */
+typedef void (*sw_progress_fn)(void* user, int64_t rows_done, int64_t rows_total);
+
 typedef struct {
     int32_t prune_mode;        /* sw_prune_mode */
     int32_t threshold;         /* > 0: use this T instead of the model's prediction (LEARNED mode) */
@@ -81,6 +85,19 @@ typedef struct {
     int32_t waves_per_cu;      /* 0 = the context's tuned value (else 8); else 1..16 stripe waves per CU */
     int32_t band_width;        /* 0 = automatic; else columns per band, a positive multiple of 64 */
     int32_t flags;             /* SW_FLAG_* bits */
+    /* Row slabs (sw_score, sw_score_dev, sw_align's score pass; paper Section 2,
+     * linear memory): the score pass runs as launches over consecutive rows of A,
+     * each starting from the previous one's last row of H and F, with the best
+     * cell so far carried over; results are identical to one launch.  0 =
+     * automatic (one launch up to 1e14 cells, else slabs of at most that);
+     * > 0 = rows per slab. */
+    int32_t slab_rows;
+    sw_progress_fn progress;   /* optional, called after each slab (NULL: none) */
+    void* progress_user;
+    /* sw_batch / sw_batch_dev in SW_PRUNE_LEARNED mode: one threshold T >= 0 per
+     * pair (n_pairs values, host memory, read during the call), used instead of
+     * the model's predictions and of `threshold`; NULL: not used. */
+    const int32_t* pair_thresholds;
 } sw_options;
 
 /* sw_batch_dev: capture the device work of the call in a HIP graph and replay
@@ -92,6 +109,33 @@ typedef struct {
  * stream. */
 #define SW_FLAG_GRAPH 1
 
+/* sw_score / sw_score_dev: run the score pass as the paper's two halves
+ * (Section 2, last paragraphs): the upper half of A's rows forward and the
+ * lower half reversed, in one launch, joined at the midline; then, when the
+ * best alignment ends below the midline, the lower half forward once more
+ * with the best score as threshold to find the endpoint.  Results equal the
+ * single pass; sw_score_result.split_case reports the paper's case.  Needs
+ * len_a >= 2; not with SW_PRUNE_LEARNED, row slabs or sw_batch
+ * (SW_EUNSUPPORTED). */
+#define SW_FLAG_HALVES 2
+
+/* sw_score / sw_score_dev / sw_align: align A against both strands of B
+ * (paper Section 3, both strands): B as given and its reverse complement
+ * (reversed, A<->T, C<->G), both in one launch.  The result is the better
+ * strand, the forward one on a tie; its strand field is 1 when it is the
+ * reverse complement, and then end_b, start_b and the CIGAR refer to the
+ * reverse complement of B (position p there is B's position len_b - 1 - p).
+ * Not with SW_PRUNE_LEARNED, SW_FLAG_HALVES or sw_batch (SW_EUNSUPPORTED). */
+#define SW_FLAG_BOTH_STRANDS 4
+
+/* Where the two-halves pass found the maximum (paper Section 2, cases a-c). */
+typedef enum {
+    SW_SPLIT_NONE = 0,    /* single pass, or score 0 */
+    SW_SPLIT_LOWER = 1,   /* (a) inside the lower half */
+    SW_SPLIT_UPPER = 2,   /* (b) inside the upper half (the first cell holding it is there) */
+    SW_SPLIT_MIDDLE = 3   /* (c) at the midpoint: the best alignment crosses the midline */
+} sw_split_case;
+
 typedef struct {
     int32_t score;             /* best local score S >= 0 */
     int32_t threshold;         /* pruning threshold T that was used (0 if none) */
@@ -99,12 +143,14 @@ typedef struct {
     int64_t end_b;             /* endpoint column (B index), -1 if S == 0 */
     int64_t cells_computed;    /* DP cells evaluated by the score pass (pruned tiles excluded) */
     int32_t fallback;          /* 1 if T exceeded the found maximum and the plain pass was rerun */
+    int32_t split_case;        /* sw_split_case (SW_FLAG_HALVES), else SW_SPLIT_NONE */
+    int32_t strand;            /* 0: B as given; 1: its reverse complement (SW_FLAG_BOTH_STRANDS) */
     int32_t reserved;
 } sw_score_result;
 
 typedef struct {
     int32_t score;
-    int32_t reserved;
+    int32_t strand;            /* 0: B as given; 1: its reverse complement (SW_FLAG_BOTH_STRANDS) */
     int64_t start_a, start_b;  /* first aligned pair, -1 if score == 0 */
     int64_t end_a, end_b;      /* last aligned pair, -1 if score == 0 */
     char* cigar;               /* NUL-terminated, owned by the library: sw_align_result_free */

@@ -40,22 +40,9 @@ using namespace swmi;
         if (e_ != hipSuccess) return fail(SW_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-namespace {
+namespace swmi {
 
 // ------------------------------------------------------------------------ midline kernel
-
-struct MidTask {
-    int64_t fwd_out, rev_out;  // out_h/out_f offsets of the forward and reversed halves
-    int64_t N;                 // columns of the sub-problem
-};
-
-struct MidResult {
-    int64_t value;
-    int64_t j;
-    int32_t type;  // 1: plain crossing, 2: deletion run through the midline
-    int32_t pad;
-    int64_t cc, dd, rr, ss;  // the four last-row values at the chosen column
-};
 
 __device__ __forceinline__ bool mid_better(int64_t v, int64_t j, int t, int64_t v2, int64_t j2, int t2) {
     return v > v2 || (v == v2 && (j < j2 || (j == j2 && t < t2)));
@@ -113,6 +100,18 @@ __global__ __launch_bounds__(256) void midline_kernel(const MidTask* __restrict_
         __syncthreads();
     }
 }
+
+hipError_t launch_midline(const MidTask* tasks, int64_t n, const int32_t* oh, const int32_t* of, int32_t g,
+                          MidResult* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(midline_kernel, dim3((unsigned)std::min<int64_t>(n, 4096)), dim3(256), 0, st, tasks, n, oh, of,
+                       g, out);
+    return hipGetLastError();
+}
+
+}  // namespace swmi
+
+namespace {
 
 // ------------------------------------------------------------------------ CIGAR pieces
 
@@ -496,9 +495,7 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
         HIP_TRY(launch_fill_i32(of, kNeg, (size_t)out_len, s));
         if ((st = run_engine(ctx, p, fa, fb, sc, eng, oh, of)) != SW_OK) return st;
         HIP_TRY(hipMemcpyAsync(d_mid, mids.data(), mids.size() * sizeof(MidTask), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(midline_kernel, dim3((unsigned)std::min<size_t>(mids.size(), 4096)), dim3(256), 0, s,
-                           d_mid, (int64_t)mids.size(), oh, of, (int32_t)g, d_res);
-        HIP_TRY(hipGetLastError());
+        HIP_TRY(launch_midline(d_mid, (int64_t)mids.size(), oh, of, (int32_t)g, d_res, s));
         std::vector<MidResult> res(mids.size());
         HIP_TRY(hipMemcpyAsync(res.data(), d_res, mids.size() * sizeof(MidResult), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -601,7 +598,18 @@ extern "C" sw_status sw_align(sw_context* ctx, const char* a, int64_t len_a, con
     sw_score_result sr;
     if ((st = sw_score(ctx, a, len_a, b, len_b, scoring, options, &sr)) != SW_OK) return st;
     out->score = sr.score;
+    out->strand = sr.strand;
     if (sr.score <= 0) return SW_OK;
+    // The reverse strand won: the later phases run on the reverse complement of B.
+    std::string rc;
+    if (sr.strand == 1) {
+        rc.resize((size_t)len_b);
+        for (int64_t j = 0; j < len_b; ++j) {
+            const char ch = (char)(b[len_b - 1 - j] & 0xDF);
+            rc[(size_t)j] = ch == 'A' ? 'T' : ch == 'C' ? 'G' : ch == 'G' ? 'C' : 'A';  // letters checked by sw_score
+        }
+        b = rc.data();
+    }
     uint8_t *d_a, *d_b;
     if ((st = upload_pair(ctx, a, len_a, b, len_b, &d_a, &d_b)) != SW_OK) return st;
     int64_t sa, sb;

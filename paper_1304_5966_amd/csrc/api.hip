@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -193,9 +194,16 @@ sw_status swmi::check_options(const sw_options* o) {
     if (o->waves_per_cu < 0 || o->waves_per_cu > 16)
         return fail(SW_EINVAL, "waves_per_cu must be 0..16 (got %d)", o->waves_per_cu);
     if (o->threshold < 0) return fail(SW_EINVAL, "threshold must be >= 0");
-    if (o->flags & ~SW_FLAG_GRAPH) return fail(SW_EINVAL, "unknown flags 0x%x", o->flags);
+    if (o->flags & ~(SW_FLAG_GRAPH | SW_FLAG_HALVES | SW_FLAG_BOTH_STRANDS))
+        return fail(SW_EINVAL, "unknown flags 0x%x", o->flags);
+    if ((o->flags & SW_FLAG_HALVES) &&
+        (o->prune_mode == SW_PRUNE_LEARNED || o->slab_rows > 0 || (o->flags & SW_FLAG_BOTH_STRANDS)))
+        return fail(SW_EUNSUPPORTED, "SW_FLAG_HALVES does not combine with SW_PRUNE_LEARNED, row slabs or both strands");
+    if ((o->flags & SW_FLAG_BOTH_STRANDS) && o->prune_mode == SW_PRUNE_LEARNED)
+        return fail(SW_EUNSUPPORTED, "SW_FLAG_BOTH_STRANDS does not combine with SW_PRUNE_LEARNED");
     if (o->band_width < 0 || o->band_width % kTick)
         return fail(SW_EINVAL, "band_width must be 0 or a positive multiple of 64 (got %d)", o->band_width);
+    if (o->slab_rows < 0) return fail(SW_EINVAL, "slab_rows must be >= 0 (got %d)", o->slab_rows);
     return SW_OK;
 }
 
@@ -277,6 +285,8 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
         pr.target = s.target;
         pr.prune = s.prune;
         pr.track = s.track;
+        pr.top_off = s.top_off;
+        pr.rows_after = s.rows_after;
         task += pr.Q * pr.n_bands;
         if (pr.n_bands > 1) lrow += pr.Q * rows_per_stripe;
         Wmax = std::max(Wmax, pr.W);
@@ -402,10 +412,18 @@ sw_status swmi::upload_engine_table(sw_context* ctx, const EnginePlan& plan, voi
     return SW_OK;
 }
 
+// Schedule-perturbation seed of the engine (a test mode): SWMI_SCHEDULE_JITTER,
+// a nonzero integer, makes waves pause at pseudo-random points; results must not
+// change.  Read at every launch.
+static uint32_t schedule_jitter() {
+    const char* v = std::getenv("SWMI_SCHEDULE_JITTER");
+    return (v && *v) ? (uint32_t)std::strtoul(v, nullptr, 10) : 0u;
+}
+
 // Kernel launches only (capturable in a HIP graph: no copies, no memsets).
 sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes,
                                       const uint8_t* b_codes, const sw_scoring* sc, void* ws, int32_t* out_h,
-                                      int32_t* out_f) {
+                                      int32_t* out_f, const int32_t* top_h, const int32_t* top_f) {
     uint8_t* base = (uint8_t*)ws;
     hipStream_t st = ctx->stream;
     HIP_TRY(launch_zero(base + plan.off_zero, plan.zero_bytes, st));
@@ -439,6 +457,12 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.pruned = (unsigned long long*)(base + plan.off_pruned);
     a.out_h = out_h;
     a.out_f = out_f;
+    a.top_h = top_h;
+    a.top_f = top_f;
+    a.jitter = schedule_jitter();
+    for (const Prob& pr : plan.probs)
+        if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))
+            return fail(SW_EINTERNAL, "engine plan: a buffer top border without its row");
     const bool cd = sc->match + sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
@@ -447,79 +471,226 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
 }
 
 sw_status swmi::run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
-                           const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f) {
+                           const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f, const int32_t* top_h,
+                           const int32_t* top_f) {
     sw_status st = upload_engine_table(ctx, plan, ws);
     if (st != SW_OK) return st;
-    return launch_engine_kernels(ctx, plan, a_codes, b_codes, sc, ws, out_h, out_f);
+    return launch_engine_kernels(ctx, plan, a_codes, b_codes, sc, ws, out_h, out_f, top_h, top_f);
 }
 
 // ------------------------------------------------------------------------ score pass
 
-static std::vector<ProbSpec> score_spec(int64_t M, int64_t N, const sw_options* o) {
-    ProbSpec s;
-    s.a_off = 0;
-    s.b_off = kBPad;
-    s.M = M;
-    s.N = N;
-    s.prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
-    s.target = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
-    s.track = 1;
-    return {s};
+// Strands of a score pass: 1 (A against B) or, with SW_FLAG_BOTH_STRANDS, 2 (also
+// A against the reverse complement of B).
+static int strands_of(const sw_options* o) { return (o && (o->flags & SW_FLAG_BOTH_STRANDS)) ? 2 : 1; }
+
+// Score workspace: [a codes][b codes, one padded copy per strand][encode flags][slab rows][engine region]
+static size_t a_code_bytes(int64_t M) { return align_up((size_t)M + 64, 256); }
+static size_t b_code_bytes(int64_t N) { return align_up((size_t)(kBPad + N + kBPadTail), 256); }
+static size_t codes_bytes(int64_t M, int64_t N, int S) {
+    return a_code_bytes(M) + (size_t)S * b_code_bytes(N) + 256;
 }
 
-// Score workspace: [a codes][b codes with padding][encode flags][engine region]
-static size_t codes_bytes(int64_t M, int64_t N) {
-    return align_up((size_t)M + 64, 256) + align_up((size_t)(kBPad + N + kBPadTail), 256) + 256;
+// One problem per strand over `rows` rows of A (from a_off) and all of B.
+static std::vector<ProbSpec> score_specs(int64_t a_off, int64_t rows, int64_t N, const sw_options* o, int S) {
+    std::vector<ProbSpec> v((size_t)S);
+    for (int s = 0; s < S; ++s) {
+        ProbSpec& p = v[(size_t)s];
+        p.a_off = a_off;
+        p.b_off = (int64_t)((size_t)s * b_code_bytes(N)) + kBPad;
+        p.M = rows;
+        p.N = N;
+        p.prune = (o && o->prune_mode != SW_PRUNE_NONE) ? 1 : 0;
+        p.target = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
+        p.track = 1;
+    }
+    return v;
 }
+
+// Row slabs: above this many cells per strand the score pass runs as several
+// launches of consecutive rows (about 30 s each at the measured rate), so that no
+// single launch keeps the device busy for minutes.
+static const double kSlabCells = 1.0e14;
+
+// Rows of A per score-pass launch; 0 = the whole matrix in one launch.
+static int64_t slab_rows_for(int64_t M, int64_t N, const sw_options* o) {
+    if (o && o->slab_rows > 0) return o->slab_rows >= M ? 0 : o->slab_rows;
+    const double cells = (double)M * (double)N * strands_of(o);
+    if (cells <= kSlabCells) return 0;
+    const int64_t n = (int64_t)std::ceil(cells / kSlabCells);
+    return (M + n - 1) / n;
+}
+
+// One slab-boundary row: {H or F} x (N + 1) columns x strands; four of them
+// (H and F, double-buffered).
+static size_t slab_row_bytes(int64_t N, int S) { return align_up((size_t)S * (size_t)(N + 1) * sizeof(int32_t), 256); }
 
 static bool uses_model(const sw_options* o) {
     return o && o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0;
 }
 
+// Engine bytes of a score pass in slabs of h rows (0: one launch): the larger of
+// the plans of a full slab and of the last one.
+static size_t score_engine_bytes(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o, int64_t h, int S) {
+    auto plan_bytes = [&](int64_t rows) {
+        return plan_engine(ctx, score_specs(0, rows, N, o, S), true, o ? o->rows_per_lane : 0,
+                           o ? o->waves_per_cu : 0, o ? o->band_width : 0)
+            .total;
+    };
+    if (!h) return plan_bytes(M);
+    const int64_t last = M - (M - 1) / h * h;
+    return std::max(plan_bytes(h), plan_bytes(last));
+}
+
 size_t swmi::score_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o) {
-    const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
-                                     o ? o->waves_per_cu : 0, o ? o->band_width : 0);
-    size_t total = codes_bytes(M, N) + p.total;
+    if (o && (o->flags & SW_FLAG_HALVES)) return halves_workspace_size(ctx, M, N, o);
+    const int S = strands_of(o);
+    const int64_t h = slab_rows_for(M, N, o);
+    size_t total = codes_bytes(M, N, S) + (h ? 4 * slab_row_bytes(N, S) : 0) + score_engine_bytes(ctx, M, N, o, h, S);
     if (uses_model(o)) total = std::max(total, predict_workspace_size(M, N, 1));
     return total;
+}
+
+static void report_progress(const sw_options* o, int64_t done, int64_t total) {
+    if (o && o->progress) o->progress(o->progress_user, done, total);
+}
+
+// Bad-letter flags of the encode kernels, copied to the host.
+static sw_status check_encoded(const uint8_t* flags_host) {
+    unsigned long long bad_a, bad_b;
+    std::memcpy(&bad_a, flags_host, 8);
+    std::memcpy(&bad_b, flags_host + 8, 8);
+    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
+    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
+    return SW_OK;
+}
+
+// The score pass as consecutive row slabs (paper Section 2, linear memory): slab
+// k covers rows [r0, r1) of A against all of B (each strand one problem of the
+// launch) and its row 0 is the previous slab's last row (H and F per column, kept
+// in the workspace).  The pruning bound of a tile counts the rows of later slabs,
+// so it stays a bound of every path through the tile.  Per strand, the best cell
+// so far becomes the next slab's target: only cells that reach it are tracked,
+// and a tie goes to the earlier slab, whose rows come first -- the
+// lexicographically first endpoint.  res[s]: strand s's result.
+static sw_status run_score_slabs(sw_context* ctx, const uint8_t* a_codes, int64_t M, const uint8_t* b_codes,
+                                 int64_t N, const sw_scoring* sc, const sw_options* o, int64_t h, int S, uint8_t* rows,
+                                 uint8_t* eng, size_t eng_bytes, ScoreOut* res) {
+    const size_t rb = slab_row_bytes(N, S);
+    int32_t* rowH[2] = {(int32_t*)rows, (int32_t*)(rows + rb)};
+    int32_t* rowF[2] = {(int32_t*)(rows + 2 * rb), (int32_t*)(rows + 3 * rb)};
+    const int32_t t_user = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
+    int32_t best[2] = {0, 0}, seen[2] = {0, 0};
+    int64_t bi[2] = {-1, -1}, bj[2] = {-1, -1};
+    unsigned long long pruned[2] = {0, 0};
+    int k = 0;
+    for (int64_t r0 = 0; r0 < M; r0 += h, ++k) {
+        const int64_t r1 = std::min(M, r0 + h);
+        std::vector<ProbSpec> specs = score_specs(r0, r1 - r0, N, o, S);
+        for (int s = 0; s < S; ++s) {
+            ProbSpec& ps = specs[(size_t)s];
+            ps.top_kind = r0 == 0 ? BORDER_ZERO : BORDER_BUF;
+            ps.top_off = r0 == 0 ? -1 : (int64_t)s * (N + 1);
+            ps.out_off = r1 < M ? (int64_t)s * (N + 1) : -1;
+            ps.rows_after = M - r1;
+            ps.target = std::max(t_user, best[s]);
+        }
+        const EnginePlan p = plan_engine(ctx, specs, true, o ? o->rows_per_lane : 0, o ? o->waves_per_cu : 0,
+                                         o ? o->band_width : 0);
+        if (p.total > eng_bytes) return fail(SW_EINTERNAL, "row slab plan exceeds its workspace");
+        sw_status st = run_engine(ctx, p, a_codes, b_codes, sc, eng, rowH[k & 1], rowF[k & 1],
+                                  r0 == 0 ? nullptr : rowH[(k + 1) & 1], r0 == 0 ? nullptr : rowF[(k + 1) & 1]);
+        if (st != SW_OK) return st;
+        ScoreOut* so;
+        if ((st = read_back(ctx, eng + p.off_outs, (size_t)S * sizeof(ScoreOut), (void**)&so)) != SW_OK) return st;
+        for (int i = 0; i < S; ++i) {
+            const int s = (int)p.order[(size_t)i];  // probs[i] is strand order[i]
+            const ScoreOut& r = so[i];
+            if (r.status) return fail(SW_EINTERNAL, "row slab %d: endpoint of the best score was not tracked", k);
+            pruned[s] += r.pruned_cells;
+            if (r.end_a >= 0 && r.score > best[s]) {
+                best[s] = r.score;
+                bi[s] = r0 + r.end_a;
+                bj[s] = r.end_b;
+            } else if (r.end_a < 0) {
+                seen[s] = std::max(seen[s], r.score);  // largest H of an untracked slab (below its target)
+            }
+        }
+        report_progress(o, r1, M);
+    }
+    for (int s = 0; s < S; ++s) {
+        ScoreOut& r = res[s];
+        r.status = 0;
+        r.pruned_cells = pruned[s];
+        if (best[s] >= seen[s]) {
+            r.score = best[s];
+            r.end_a = bi[s];
+            r.end_b = bj[s];
+        } else {  // a learned target missed: the largest H computed, without an endpoint
+            r.score = seen[s];
+            r.end_a = -1;
+            r.end_b = -1;
+        }
+    }
+    return SW_OK;
 }
 
 static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
                                 const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
                                 sw_score_result* out) {
-    const EnginePlan p = plan_engine(ctx, score_spec(M, N, o), true, o ? o->rows_per_lane : 0,
-                                     o ? o->waves_per_cu : 0, o ? o->band_width : 0);
-    const size_t need = codes_bytes(M, N) + p.total;
+    const int S = strands_of(o);
+    const int64_t h = slab_rows_for(M, N, o);
+    const size_t rows_bytes = h ? 4 * slab_row_bytes(N, S) : 0;
+    const size_t cb = codes_bytes(M, N, S);
+    const size_t need = cb + rows_bytes + score_engine_bytes(ctx, M, N, o, h, S);
     if (ws_bytes < need) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     uint8_t* a_codes = (uint8_t*)ws;
-    uint8_t* b_codes = a_codes + align_up((size_t)M + 64, 256);
-    uint8_t* flags = (uint8_t*)ws + codes_bytes(M, N) - 256;
-    uint8_t* eng = (uint8_t*)ws + codes_bytes(M, N);
+    uint8_t* b_codes = a_codes + a_code_bytes(M);
+    uint8_t* flags = (uint8_t*)ws + cb - 256;
+    uint8_t* rows = (uint8_t*)ws + cb;
+    uint8_t* eng = rows + rows_bytes;
     hipStream_t st = ctx->stream;
     HIP_TRY(launch_zero(flags, 256, st));
     HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, 0, (unsigned long long*)flags, st));
-    HIP_TRY(launch_encode(d_b, N, b_codes, kBPad, kBPadTail, 0, (unsigned long long*)(flags + 8), st));
-    sw_status s = run_engine(ctx, p, a_codes, b_codes, sc, eng, nullptr, nullptr);
-    if (s != SW_OK) return s;
+    for (int s = 0; s < S; ++s)  // strand 1: the reverse complement of B
+        HIP_TRY(launch_encode(d_b, N, b_codes + (size_t)s * b_code_bytes(N), kBPad, kBPadTail,
+                              s ? (ENC_REVERSE | ENC_COMPLEMENT) : 0, (unsigned long long*)(flags + 8), st));
     uint8_t* hm = (uint8_t*)ctx->host_misc;
-    HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hm + 64, eng + p.off_outs, sizeof(ScoreOut), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    unsigned long long bad_a, bad_b;
-    std::memcpy(&bad_a, hm, 8);
-    std::memcpy(&bad_b, hm + 8, 8);
-    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
-    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
-    ScoreOut so;
-    std::memcpy(&so, hm + 64, sizeof so);
-    if (so.status) return fail(SW_EINTERNAL, "score pass: endpoint of the best score was not tracked");
+    ScoreOut so[2];
+    sw_status s;
+    if (h) {
+        // letters first: a bad letter must not run a whole slab sequence
+        HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((s = check_encoded(hm)) != SW_OK) return s;
+        if ((s = run_score_slabs(ctx, a_codes, M, b_codes, N, sc, o, h, S, rows, eng,
+                                 ws_bytes - (size_t)(eng - (uint8_t*)ws), so)) != SW_OK)
+            return s;
+    } else {
+        const EnginePlan p = plan_engine(ctx, score_specs(0, M, N, o, S), true, o ? o->rows_per_lane : 0,
+                                         o ? o->waves_per_cu : 0, o ? o->band_width : 0);
+        if ((s = run_engine(ctx, p, a_codes, b_codes, sc, eng, nullptr, nullptr)) != SW_OK) return s;
+        HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hm + 64, eng + p.off_outs, (size_t)S * sizeof(ScoreOut), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((s = check_encoded(hm)) != SW_OK) return s;
+        for (int i = 0; i < S; ++i) std::memcpy(&so[p.order[(size_t)i]], hm + 64 + i * sizeof(ScoreOut), sizeof(ScoreOut));
+        for (int i = 0; i < S; ++i)
+            if (so[i].status) return fail(SW_EINTERNAL, "score pass: endpoint of the best score was not tracked");
+        report_progress(o, M, M);
+    }
+    // the better strand; the forward one on a tie
+    const int w = (S == 2 && so[1].score > so[0].score) ? 1 : 0;
     std::memset(out, 0, sizeof *out);
-    out->score = so.score;
-    out->end_a = so.end_a;
-    out->end_b = so.end_b;
+    out->score = so[w].score;
+    out->end_a = so[w].end_a;
+    out->end_b = so[w].end_b;
+    out->strand = w;
     out->threshold = (o && o->prune_mode == SW_PRUNE_LEARNED) ? o->threshold : 0;
-    const unsigned long long total = (unsigned long long)M * (unsigned long long)N;
-    out->cells_computed = (int64_t)(so.pruned_cells >= total ? 0 : total - so.pruned_cells);
+    const unsigned long long total = (unsigned long long)M * (unsigned long long)N * (unsigned long long)S;
+    unsigned long long pruned = 0;
+    for (int i = 0; i < S; ++i) pruned += so[i].pruned_cells;
+    out->cells_computed = (int64_t)(pruned >= total ? 0 : total - pruned);
     return SW_OK;
 }
 
@@ -532,6 +703,7 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
 sw_status swmi::run_score(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
                           const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
                           sw_score_result* out) {
+    if (o && (o->flags & SW_FLAG_HALVES)) return run_score_halves(ctx, d_a, M, d_b, N, sc, o, ws, ws_bytes, out);
     if (!o || o->prune_mode != SW_PRUNE_LEARNED) return run_score_once(ctx, d_a, M, d_b, N, sc, o, ws, ws_bytes, out);
     sw_options ol = *o;
     if (ol.threshold == 0) {

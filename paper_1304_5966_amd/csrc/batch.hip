@@ -296,7 +296,7 @@ static sw_status pairs_of(const int64_t* offs_a, const int64_t* offs_b, int32_t 
 }
 
 static bool batch_uses_model(const sw_options* o) {
-    return o && o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0;
+    return o && o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0 && !o->pair_thresholds;
 }
 
 extern "C" size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b,
@@ -328,7 +328,11 @@ static sw_status batch_all(sw_context* ctx, const uint8_t* d_a, const uint8_t* d
                            size_t ws_bytes, sw_score_result* out) {
     const int32_t n = (int32_t)as.size();
     std::vector<int32_t> T;
-    if (batch_uses_model(o)) {
+    if (o && o->prune_mode == SW_PRUNE_LEARNED && o->pair_thresholds) {
+        T.assign(o->pair_thresholds, o->pair_thresholds + n);
+        for (int32_t p = 0; p < n; ++p)
+            if (T[(size_t)p] < 0) return fail(SW_EINVAL, "pair_thresholds[%d] is negative", p);
+    } else if (batch_uses_model(o)) {
         if (!o->model) return fail(SW_EINVAL, "SW_PRUNE_LEARNED needs a model or a threshold");
         std::vector<int64_t> oa((size_t)n + 1), ob((size_t)n + 1);
         // predict_thresholds takes offsets of consecutive pairs: pass per-pair starts via
@@ -414,6 +418,8 @@ extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, cons
     sw_status st;
     if ((st = check_scoring(scoring)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if (options && (options->flags & (SW_FLAG_HALVES | SW_FLAG_BOTH_STRANDS)))
+        return fail(SW_EUNSUPPORTED, "sw_batch: SW_FLAG_HALVES and SW_FLAG_BOTH_STRANDS are single-pair options");
     std::vector<int64_t> as, al, bs, bl;
     if ((st = pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl)) != SW_OK) return st;
     if (n_pairs > 0 && (!d_seqs_a || !d_seqs_b)) return fail(SW_EINVAL, "sw_batch_dev: NULL sequences");
@@ -429,6 +435,8 @@ extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t
     sw_status st;
     if ((st = check_scoring(scoring)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if (options && (options->flags & (SW_FLAG_HALVES | SW_FLAG_BOTH_STRANDS)))
+        return fail(SW_EUNSUPPORTED, "sw_batch: SW_FLAG_HALVES and SW_FLAG_BOTH_STRANDS are single-pair options");
     std::vector<int64_t> as, al, bs, bl;
     if ((st = pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl)) != SW_OK) return st;
     if (n_pairs == 0) return SW_OK;

@@ -105,6 +105,21 @@ __device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need,
     asm volatile("" ::: "memory");
 }
 
+// Schedule perturbation (a test mode; off when seed == 0): a wave-uniform
+// pseudo-random pause, so that tests see the hand-off protocol under other
+// interleavings of producers, consumers and slot reuse.  About one call in
+// eight pauses, for up to 15 x 127 x 64 cycles.
+__device__ __forceinline__ void jitter_pause(uint32_t seed, int64_t task, int32_t step) {
+    if (!seed) return;
+    uint32_t h = seed ^ (uint32_t)task * 0x9E3779B1u ^ (uint32_t)step * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h = __builtin_amdgcn_readfirstlane(h);
+    if ((h & 7) != 0) return;
+    for (uint32_t i = 0; i < ((h >> 3) & 15); ++i) __builtin_amdgcn_s_sleep(127);
+}
+
 // Four score bytes s(a, c) + bias for c = 0..3 (pad row: all -128).
 __device__ __forceinline__ uint32_t row_table(int code, int match, int mismatch, int bias) {
     if (code > 3) return kPadTable;
@@ -375,6 +390,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         if (lane == 0) tk = atomicAdd(p.ticket, 1u);
         const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);  // the ticket
         if (task >= p.n_tickets) break;
+        jitter_pause(p.jitter, task, -1);
         const Ticket tkt = p.tickets[task];
         const int64_t pi = tkt.pi;
         const Prob pr = p.probs[pi];
@@ -466,6 +482,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             const int rel = base + lane;
             if (rel >= W) return make_int2(NEGV, NEGV);
             if (q == 0) {
+                if (pr.top_kind == BORDER_BUF) {
+                    // a row of a larger matrix: H and F there give the next row's F-candidate
+                    const int h = p.top_h[pr.top_off + c0 + rel + 1];
+                    const int f = p.top_f[pr.top_off + c0 + rel + 1];
+                    return make_int2(h, max(f - p.ext, h - p.open));
+                }
                 const int h = border_h(pr.top_kind, pr.top_open, p.ext, c0 + rel + 1);
                 if (pr.top_kind == BORDER_GAP) return make_int2(h, h - p.open);
                 return make_int2(h, LOCAL ? 0 : kNeg);
@@ -477,7 +499,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         {
             int h_diag = 0;
             if (q == 0) {
-                h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
+                if (pr.top_kind == BORDER_BUF) h_diag = p.top_h[pr.top_off + c0];
+                else h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
             } else if (prod_active) {
                 wait_at_least(prod_prog, 1, prod_seen);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
@@ -594,7 +617,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     hm = wave_max(hm);
                     if (LOCAL) hm = max(hm, 0);
                     if (pr.prune) {
-                        const int64_t rows_left = pr.M - R0;
+                        const int64_t rows_left = pr.M + pr.rows_after - R0;
                         const int64_t cols_left = pr.N - (c.col0 - (kTick - 1));
                         const int64_t ub = (int64_t)hm + (int64_t)p.match * min(rows_left, cols_left);
                         skip = ub < (int64_t)L;
@@ -757,6 +780,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 }
                 if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, o);
             }
+            jitter_pause(p.jitter, task, tau);
             publish_count(p.progress + task, min(kTick * tau + 1, W));
             if (has_cons) {
                 const int32_t cs = __builtin_amdgcn_readfirstlane(cons_pf);
@@ -814,18 +838,21 @@ __device__ __forceinline__ uint8_t encode_letter(uint8_t ch, bool& ok) {
     return ok ? code : kPadCode;
 }
 
+// mode: bit 0 reverses the sequence, bit 1 complements it (A<->T, C<->G: code ^ 3).
 __global__ void encode_kernel(const uint8_t* __restrict__ src, int64_t n, uint8_t* __restrict__ dst,
-                              int64_t pad_before, int64_t pad_after, int reverse, unsigned long long* bad) {
+                              int64_t pad_before, int64_t pad_after, int mode, unsigned long long* bad) {
     const int64_t total = pad_before + n + pad_after;
+    const uint8_t flip = (mode & 2) ? 3 : 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = i - pad_before;
         uint8_t code = kPadCode;
         if (j >= 0 && j < n) {
-            const int64_t sj = reverse ? n - 1 - j : j;
+            const int64_t sj = (mode & 1) ? n - 1 - j : j;
             bool ok;
             code = encode_letter(src[sj], ok);
             if (!ok) atomicMax(bad, (1ull << 62) - (unsigned long long)sj);  // largest value = first offset
+            else code ^= flip;
         }
         dst[i] = code;
     }
@@ -896,7 +923,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
             ScoreOut o;
             o.pruned_cells = pruned ? pruned[pi] : 0;
             o.status = 0;
-            const bool local = pr.top_kind == BORDER_ZERO;
+            const bool local = pr.left_kind == BORDER_ZERO;  // the local recurrence has zero borders
             if (local && s_v[0] < pr.target) {
                 // Below the target nothing was tracked: report the largest H seen
                 // (a lower bound of the optimum), without an endpoint.
@@ -925,11 +952,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
 // ------------------------------------------------------------------------ launchers
 
 hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
-                         int reverse, unsigned long long* bad, hipStream_t st) {
+                         int mode, unsigned long long* bad, hipStream_t st) {
     const int64_t total = pad_before + n + pad_after;
     const int blocks = (int)min((int64_t)4096, (total + 255) / 256);
     hipLaunchKernelGGL(encode_kernel, dim3(max(blocks, 1)), dim3(256), 0, st, src, n, dst, pad_before, pad_after,
-                       reverse, bad);
+                       mode, bad);
     return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ struct ProbSpec {
     int32_t target = 0, prune = 0, track = 1;
     int64_t d_lo = -kNoBand, d_hi = kNoBand;
     int64_t out_off = -1;
+    int64_t top_off = -1;    // BORDER_BUF top: index of row 0's column 0 in the launch's top_h/top_f
+    int64_t rows_after = 0;  // rows of the whole matrix below this problem (row slabs)
 };
 
 // Decomposition and workspace layout of one engine launch.
@@ -93,12 +95,14 @@ EnginePlan plan_engine(const sw_context* ctx, const std::vector<ProbSpec>& specs
 // Runs a planned launch inside workspace `ws` (plan.total bytes): clears the
 // counters, copies the table, launches the engine and the per-problem reduction
 // into the ScoreOut array at ws + plan.off_outs (ordered like plan.probs).
+// top_h/top_f: row 0 of BORDER_BUF problems (H and F per column, as out_h/out_f hold them).
 sw_status run_engine(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes, const uint8_t* b_codes,
-                     const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f);
+                     const sw_scoring* sc, void* ws, int32_t* out_h, int32_t* out_f,
+                     const int32_t* top_h = nullptr, const int32_t* top_f = nullptr);
 sw_status upload_engine_table(sw_context* ctx, const EnginePlan& plan, void* ws);
 sw_status launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes,
                                 const uint8_t* b_codes, const sw_scoring* sc, void* ws, int32_t* out_h,
-                                int32_t* out_f);
+                                int32_t* out_f, const int32_t* top_h = nullptr, const int32_t* top_f = nullptr);
 // Copies `bytes` from device to the context's pinned buffer and waits for the stream.
 sw_status read_back(sw_context* ctx, const void* dev, size_t bytes, void** host);
 
@@ -116,5 +120,10 @@ size_t predict_workspace_size(int64_t max_M, int64_t max_N, int32_t n);
 sw_status predict_thresholds(sw_context* ctx, const sw_model* m, const uint8_t* d_a, const int64_t* offs_a,
                              const uint8_t* d_b, const int64_t* offs_b, int32_t n, void* ws, size_t ws_bytes,
                              std::vector<int32_t>& T);
+
+// Two-halves score pass (halves.hip; SW_FLAG_HALVES).
+size_t halves_workspace_size(const sw_context* ctx, int64_t M, int64_t N, const sw_options* o);
+sw_status run_score_halves(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
+                           const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes, sw_score_result* out);
 
 }  // namespace swmi

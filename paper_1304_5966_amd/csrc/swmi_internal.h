@@ -21,7 +21,9 @@ constexpr int64_t kNoBand = (int64_t)1 << 62;
 enum BorderKind : int32_t {
     BORDER_ZERO = 0,  // local alignment: H = 0
     BORDER_NEG = 1,   // anchored: H = -inf (the corner H(0,0) stays 0)
-    BORDER_GAP = 2    // a gap run from the corner: H = -(open_cost + ext * k)
+    BORDER_GAP = 2,   // a gap run from the corner: H = -(open_cost + ext * k)
+    BORDER_BUF = 3    // top border only: row 0 is a row of a larger matrix, given as H and F
+                      // (the vertical-gap state) per column 0..N in EngineArgs::top_h/top_f
 };
 
 // One DP problem of a launch.  Rows are the `a` codes, columns the `b` codes;
@@ -35,6 +37,9 @@ struct Prob {
     int64_t lbuf_off;    // first row of this problem in the band-boundary buffer
     int64_t out_off;     // last-row outputs at out_h/out_f[out_off + j], j = 0..N; -1: none
     int64_t d_lo, d_hi;  // diagonal band j - i kept by the global recurrence (kNoBand: all)
+    int64_t top_off;     // BORDER_BUF: row 0's column 0 at top_h/top_f[top_off]
+    int64_t rows_after;  // rows of the whole matrix below this problem's last row (row slabs):
+                         // a path through a tile may continue there, so its bound counts them
     int32_t top_kind, left_kind;
     int32_t top_open, left_open;  // gap-open cost of BORDER_GAP borders
     int32_t target;      // tiles whose upper bound is below max(running best, target) are skipped
@@ -102,6 +107,9 @@ struct EngineArgs {
     unsigned long long* pruned;  // [n_probs] cells skipped
     int32_t* out_h;          // last-row H of problems with out_off >= 0
     int32_t* out_f;          // last-row F (deletion-ending) of the same
+    const int32_t* top_h;    // row 0 of BORDER_BUF problems: H
+    const int32_t* top_f;    // and F (deletion-ending), as out_h/out_f write them
+    uint32_t jitter;         // schedule-perturbation seed (tests; 0 = off)
 };
 
 struct ScoreOut {
@@ -111,8 +119,29 @@ struct ScoreOut {
     unsigned long long pruned_cells;
 };
 
+// Midline of a split (Myers-Miller; the paper's two-halves score pass): the
+// forward half's last row (CC = H, DD = deletion-ending F) at out offset fwd_out
+// + j and the reversed half's (RR, SS) at rev_out + (N - j), j = 0..N.
+struct MidTask {
+    int64_t fwd_out, rev_out;  // out_h/out_f offsets of the forward and reversed halves
+    int64_t N;                 // columns
+};
+
+struct MidResult {
+    int64_t value;           // max over j of CC + RR (plain crossing) and DD + SS + g (a deletion run through it)
+    int64_t j;               // the first column reaching it (a plain crossing first at equal columns)
+    int32_t type;            // 1: plain crossing, 2: deletion run through the midline
+    int32_t pad;
+    int64_t cc, dd, rr, ss;  // the four last-row values at that column
+};
+
+hipError_t launch_midline(const MidTask* tasks, int64_t n, const int32_t* oh, const int32_t* of, int32_t g,
+                          MidResult* out, hipStream_t st);
+
+// mode: ENC_REVERSE and/or ENC_COMPLEMENT (0: the letters as they are).
+enum { ENC_REVERSE = 1, ENC_COMPLEMENT = 2 };
 hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
-                         int reverse, unsigned long long* bad, hipStream_t st);
+                         int mode, unsigned long long* bad, hipStream_t st);
 hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
                               const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad,
                               hipStream_t st);

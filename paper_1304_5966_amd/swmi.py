@@ -24,6 +24,9 @@ SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EUNSUPPORTED, SW_EINTERNAL = 0, -1, 
 PRUNE_NONE, PRUNE_BEST, PRUNE_LEARNED = 0, 1, 2
 TUNE_PAIR_SMALL, TUNE_PAIR_LARGE, TUNE_PAIR_HUGE, TUNE_BATCH = 0, 1, 2, 3
 FLAG_GRAPH = 1  # SW_FLAG_GRAPH
+FLAG_HALVES = 2  # SW_FLAG_HALVES
+FLAG_BOTH_STRANDS = 4  # SW_FLAG_BOTH_STRANDS
+SPLIT_NONE, SPLIT_LOWER, SPLIT_UPPER, SPLIT_MIDDLE = 0, 1, 2, 3
 DEFAULT_SCORING = (1, 3, 5, 2)
 
 
@@ -38,22 +41,27 @@ class Scoring(ctypes.Structure):
                 ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("prune_mode", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("rows_per_lane", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("band_width", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("slab_rows", ctypes.c_int32),
+                ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
+                ("pair_thresholds", ctypes.POINTER(ctypes.c_int32))]
 
 
 class ScoreResult(ctypes.Structure):
     _fields_ = [("score", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("end_a", ctypes.c_int64), ("end_b", ctypes.c_int64),
                 ("cells_computed", ctypes.c_int64), ("fallback", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("split_case", ctypes.c_int32), ("strand", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class AlignResult(ctypes.Structure):
-    _fields_ = [("score", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("score", ctypes.c_int32), ("strand", ctypes.c_int32),
                 ("start_a", ctypes.c_int64), ("start_b", ctypes.c_int64),
                 ("end_a", ctypes.c_int64), ("end_b", ctypes.c_int64),
                 ("cigar", ctypes.c_void_p), ("cigar_len", ctypes.c_int64)]
@@ -141,9 +149,20 @@ def _bytes(x) -> bytes:
 
 
 def _options(prune=PRUNE_NONE, threshold=0, rows_per_lane=0, waves_per_cu=0, band_width=0,
-             model=None, graph=False) -> Options:
-    return Options(int(prune), int(threshold), model, int(rows_per_lane), int(waves_per_cu),
-                   int(band_width), FLAG_GRAPH if graph else 0)
+             model=None, graph=False, slab_rows=0, progress=None, halves=False, both_strands=False,
+             pair_thresholds=None) -> Options:
+    """progress: optional callable(rows_done, rows_total), called after each row slab.
+    pair_thresholds: batch calls in PRUNE_LEARNED mode, one threshold per pair."""
+    op = Options(int(prune), int(threshold), model, int(rows_per_lane), int(waves_per_cu),
+                 int(band_width), (FLAG_GRAPH if graph else 0) | (FLAG_HALVES if halves else 0)
+                 | (FLAG_BOTH_STRANDS if both_strands else 0), int(slab_rows))
+    if progress is not None:
+        op.progress = PROGRESS_FN(lambda _user, done, total: progress(int(done), int(total)))
+    if pair_thresholds is not None:
+        arr = np.ascontiguousarray(pair_thresholds, dtype=np.int32)
+        op._pair_thresholds = arr  # keeps the array alive as long as the options
+        op.pair_thresholds = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return op
 
 
 @dataclass
@@ -154,6 +173,8 @@ class Score:
     cells_computed: int = 0
     threshold: int = 0
     fallback: int = 0
+    split_case: int = 0
+    strand: int = 0
 
     def key(self):
         return (self.score, self.end_a, self.end_b)
@@ -167,14 +188,16 @@ class Alignment:
     end_a: int
     end_b: int
     cigar: str
+    strand: int = 0
 
 
 def _score_of(r: ScoreResult) -> Score:
-    return Score(r.score, r.end_a, r.end_b, r.cells_computed, r.threshold, r.fallback)
+    return Score(r.score, r.end_a, r.end_b, r.cells_computed, r.threshold, r.fallback, r.split_case, r.strand)
 
 
 _SCORE_DTYPE = np.dtype([("score", "<i4"), ("threshold", "<i4"), ("end_a", "<i8"), ("end_b", "<i8"),
-                         ("cells_computed", "<i8"), ("fallback", "<i4"), ("reserved", "<i4")])
+                         ("cells_computed", "<i8"), ("fallback", "<i4"), ("split_case", "<i4"),
+                         ("strand", "<i4"), ("reserved", "<i4")])
 assert _SCORE_DTYPE.itemsize == ctypes.sizeof(ScoreResult)
 
 
@@ -194,7 +217,7 @@ class BatchResults(Sequence):
             return [self[j] for j in range(*i.indices(len(self)))]
         r = self.array[i]
         return Score(int(r["score"]), int(r["end_a"]), int(r["end_b"]), int(r["cells_computed"]),
-                     int(r["threshold"]), int(r["fallback"]))
+                     int(r["threshold"]), int(r["fallback"]), int(r["split_case"]), int(r["strand"]))
 
     def __eq__(self, other):
         return list(self) == list(other)
@@ -254,7 +277,7 @@ class Context:
                             ctypes.byref(_options(**opts)), ctypes.byref(r)))
         try:
             cig = ctypes.string_at(r.cigar, r.cigar_len).decode() if r.cigar else ""
-            return Alignment(r.score, r.start_a, r.start_b, r.end_a, r.end_b, cig)
+            return Alignment(r.score, r.start_a, r.start_b, r.end_a, r.end_b, cig, r.strand)
         finally:
             lib.sw_align_result_free(ctypes.byref(r))
 

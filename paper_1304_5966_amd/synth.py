@@ -164,11 +164,16 @@ def mutate(rng: np.random.Generator, src: np.ndarray, sub_rate: float, indel_rat
 
 @dataclass
 class Planted:
-    """Where a mutated copy of ``a[a_off : a_off + a_len]`` sits in ``b`` (from ``b_off``)."""
+    """Where a mutated copy of ``a[a_off : a_off + a_len]`` sits in ``b`` (from ``b_off``).
+
+    strand 1: the copy sits in the reverse complement of ``b`` (``b_off`` and the
+    transcript refer to that sequence).
+    """
     a_off: int
     a_len: int
     b_off: int
     transcript: Transcript
+    strand: int = 0
 
 
 @dataclass
@@ -319,6 +324,16 @@ def config4_pair(i: int, seed: int = SEED_CONFIG4_EVAL, lo: int = 1_000_000,
     return p
 
 
+def config4_meta(i: int, seed: int = SEED_CONFIG4_EVAL, lo: int = 1_000_000,
+                 hi: int = 4_000_000) -> tuple:
+    """(|A|, |B|, homologous) of ``config4_pair(i)`` without generating its letters
+    (the same first draws of the pair's generator)."""
+    rng = rng_for(seed, i)
+    la = int(rng.integers(lo, hi + 1))
+    lb = int(rng.integers(lo, hi + 1))
+    return la, lb, bool(rng.random() < 0.4)
+
+
 def config5(seed: int = SEED_CONFIG5, len_a: int = 32_000_000, len_b: int = 28_000_000,
             n_seg: int = 40) -> Pair:
     """Genome-scale pair: A with GC-rich islands; B from shuffled, partly reverse-complemented pieces of A.
@@ -349,7 +364,7 @@ def config5(seed: int = SEED_CONFIG5, len_a: int = 32_000_000, len_b: int = 28_0
     n_rc = max(1, int(round(0.1 * n_seg)))
     rc = np.zeros(n_seg, dtype=bool)
     rc[rng.choice(n_seg, size=n_rc, replace=False)] = True
-    pieces, planted = [], []
+    pieces, planted, planted_rc = [], [], []
     b_pos = 0
     for k in order.tolist():
         seg = a[offs[k]:offs[k] + int(seg_lens[k])]
@@ -358,6 +373,11 @@ def config5(seed: int = SEED_CONFIG5, len_a: int = 32_000_000, len_b: int = 28_0
         mut, tr = mutate(rng, seg, 0.02, 0.002)
         if not rc[k]:
             planted.append(Planted(offs[k], int(seg_lens[k]), b_pos, tr))
+        else:
+            # in the reverse complement of B the copy reads forward against A: the transcript
+            # reversed (complementing both sides keeps every '=' and 'X')
+            rev = Transcript(tr.ops[::-1].copy(), tr.lens[::-1].copy())
+            planted_rc.append((offs[k], int(seg_lens[k]), b_pos + mut.size, rev))
         pieces.append(mut)
         b_pos += mut.size
     b = np.concatenate(pieces)
@@ -372,6 +392,9 @@ def config5(seed: int = SEED_CONFIG5, len_a: int = 32_000_000, len_b: int = 28_0
         planted = keep
     else:
         b = np.concatenate((b, random_dna(rng, len_b - b.size)))
+    for a_off, a_len, b_end, rev in planted_rc:
+        if b_end <= len_b:  # copies cut by the trim are left out
+            planted.append(Planted(a_off, a_len, len_b - b_end, rev, strand=1))
     p = Pair(a, b, planted, True)
     p.tag = "config5"
     return p

@@ -176,3 +176,23 @@ def test_batch_slot_reuse_across_problems(ctx, orc, monkeypatch):
             got = ctx.batch(pairs, rows_per_lane=R, waves_per_cu=1)
             bad = [i for i, (g, e) in enumerate(zip(got, exp)) if g.key() != e]
             assert not bad, (R, rep, bad[:5])
+
+
+def test_batch_per_pair_thresholds(ctx, orc):
+    """PRUNE_LEARNED with one threshold per pair: thresholds at or below the true score are
+    reached in one pass; thresholds above it miss and rerun; results are exact either way."""
+    from paper_1304_5966_amd import swmi
+    rng = np.random.default_rng(8080)
+    pairs = []
+    for k in range(24):
+        la, lb = int(rng.integers(200, 3000)), int(rng.integers(200, 3000))
+        p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.1) if k % 2 else \
+            synth.random_pair(int(rng.integers(1 << 30)), la, lb)
+        pairs.append((p.a.tobytes(), p.b.tobytes()))
+    exp = [orc.sw_score(a, b) for a, b in pairs]
+    T = [s if k % 3 == 0 else (s // 2 if k % 3 == 1 else s + 5) for k, (s, _, _) in enumerate(exp)]
+    res = ctx.batch(pairs, prune=swmi.PRUNE_LEARNED, pair_thresholds=T)
+    assert res.keys() == exp
+    for k, r in enumerate(res):
+        assert r.threshold == T[k]
+        assert r.fallback == (1 if T[k] > exp[k][0] else 0), k

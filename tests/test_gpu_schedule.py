@@ -1,0 +1,83 @@
+"""The stripe hand-off protocol under perturbed schedules (SWMI_SCHEDULE_JITTER).
+
+With a nonzero seed every wave pauses at pseudo-random points: when it takes a
+ticket and before it publishes a tick's column count.  Producers then run late
+or early against their consumers, slots are reused at other moments and the
+running best grows in another order.  Results depend on none of that (pruning
+and the hand-off are exact), so every case must still equal the oracle bit for
+bit.  Cases: single pairs over many stripes and bands with few resident waves
+(slot reuse), pruning on, row slabs, a mixed batch, and a whole alignment
+(reverse pass and reconstruction levels).  Stops at the first mismatch.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1304_5966_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SEEDS = [1, 7, 12345]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1304_5966_amd import swmi
+    c = swmi.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture
+def jitter(request):
+    os.environ["SWMI_SCHEDULE_JITTER"] = str(request.param)
+    yield request.param
+    os.environ.pop("SWMI_SCHEDULE_JITTER", None)
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("jitter", SEEDS, indirect=True)
+def test_pairs_under_jitter(ctx, orc, jitter):
+    rng = np.random.default_rng(jitter)
+    for t in range(6):
+        la, lb = int(rng.integers(500, 4000)), int(rng.integers(300, 3000))
+        p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.1) if t % 2 else \
+            synth.random_pair(int(rng.integers(1 << 30)), la, lb)
+        a, b = p.a.tobytes(), p.b.tobytes()
+        exp = orc.sw_score(a, b)
+        for opts in (dict(rows_per_lane=4, waves_per_cu=1, band_width=256), dict(prune=1, band_width=640),
+                     dict(rows_per_lane=6, slab_rows=700, prune=1)):
+            _case(f"jitter={jitter} {la}x{lb} t={t} {opts}")
+            assert ctx.score(a, b, **opts).key() == exp, opts
+
+
+@pytest.mark.parametrize("jitter", SEEDS[:2], indirect=True)
+def test_batch_under_jitter(ctx, orc, jitter):
+    rng = np.random.default_rng(100 + jitter)
+    pairs = []
+    for k in range(40):
+        la, lb = int(rng.integers(1, 2500)), int(rng.integers(1, 2500))
+        p = synth.homologous_pair(int(rng.integers(1 << 30)), la, lb, 0.15) if k % 2 else \
+            synth.random_pair(int(rng.integers(1 << 30)), la, lb)
+        pairs.append((p.a.tobytes(), p.b.tobytes()))
+    _case(f"jitter={jitter} batch of {len(pairs)}")
+    got = ctx.batch(pairs, rows_per_lane=4, waves_per_cu=2).keys()
+    assert got == [orc.sw_score(a, b) for a, b in pairs]
+
+
+@pytest.mark.parametrize("jitter", SEEDS[:1], indirect=True)
+def test_alignment_under_jitter(ctx, orc, jitter):
+    p = synth.homologous_pair(2718, 6000, 5200, 0.06)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    exp = orc.sw_align(a, b)
+    _case(f"jitter={jitter} alignment 6000x5200")
+    al = ctx.align(a, b, rows_per_lane=4)
+    assert (al.score, al.start_a, al.start_b, al.end_a, al.end_b, al.cigar) == \
+        (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)

@@ -66,3 +66,31 @@ def test_config3_shape():
     assert lens.min() >= 100 and lens.max() <= 20_000
     # log-uniform: median near sqrt(100 * 20000) ~ 1414
     assert 900 < np.median(lens) < 2200
+
+
+def test_genome_scale_planted_copies_on_both_strands():
+    """Every planted copy of the genome-scale generator replays against its strand of B:
+    forward copies in B, reverse-complemented ones in the reverse complement of B."""
+    p = synth.config5(len_a=400_000, len_b=350_000, n_seg=10)
+    rcb = synth.reverse_complement(p.b)
+    strands = {pl.strand for pl in p.planted}
+    assert strands == {0, 1}
+    for pl in p.planted:
+        bb = p.b if pl.strand == 0 else rcb
+        i, j = _apply(p.a[pl.a_off:], bb[pl.b_off:], pl.transcript)
+        assert i == pl.a_len
+
+
+def test_learned_set_metadata_matches_the_pairs():
+    for i in (0, 1, 7, 123):
+        la, lb, hom = synth.config4_meta(i)
+        p = synth.config4_pair(i)
+        assert (p.a.size, p.b.size, p.homologous) == (la, lb, hom)
+
+
+def test_stratified_subset_keeps_the_mix():
+    from paper_1304_5966_amd import eval_learned
+    idx = eval_learned.stratified_subset(200)
+    assert len(idx) == len(set(idx)) == 200 and idx == sorted(idx)
+    assert sum(synth.config4_meta(i)[2] for i in idx) == 80
+    assert eval_learned.stratified_subset(200) == idx
