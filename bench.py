@@ -12,8 +12,9 @@ Extra legs (reported in the same line, not in ``value``): the same pass with
 block pruning; the whole alignment of the pair (score pass, start pass,
 Myers-Miller reconstruction) timed by phase; the 20 000-pair batch; the
 learned threshold; and the CPU oracle timed on a bounded crop of the same pair.
-``--only batched|learned|align`` runs one leg alone and prints its JSON (for
-profiling a leg by itself).
+``--only batched|learned|align|genome`` runs one leg alone and prints its JSON
+(for profiling a leg by itself).  The genome leg is the score pass of the
+32 Mbp x 28 Mbp genome-scale pair with running-best pruning, in row slabs.
 """
 from __future__ import annotations
 
@@ -128,11 +129,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (shape 8 rows/lane, 8 waves/CU)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the pruned, batched and learned legs")
-    ap.add_argument("--learned-pairs", type=int, default=6)
+    ap.add_argument("--learned-pairs", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--seq-sample", type=int, default=2000)
-    ap.add_argument("--only", choices=("batched", "learned", "align"), default=None,
+    ap.add_argument("--no-genome", action="store_true", help="skip the genome-scale leg (about 4.5 minutes)")
+    ap.add_argument("--only", choices=("batched", "learned", "align", "genome"), default=None,
                     help="run one extra leg alone and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -153,6 +155,9 @@ def main():
         return
 
     opts = dict(rows_per_lane=args.rows_per_lane, waves_per_cu=args.waves_per_cu)
+    if args.only == "genome":
+        print(json.dumps(genome_leg(swmi.Context(0), torch, swmi, synth)), flush=True)
+        return
     if args.only in ("batched", "learned"):
         ctx = swmi.Context(0)
         fixed = bool(args.rows_per_lane or args.waves_per_cu)
@@ -241,6 +246,8 @@ def main():
         line["alignment"] = alignment_leg(ctx, torch, pair, d_a, d_b, opts)
         line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)
         line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
+        if not args.no_genome:
+            line["genome_scale"] = genome_leg(ctx, torch, swmi, synth)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(pair)
@@ -286,6 +293,33 @@ def alignment_leg(ctx, torch, pair, d_a, d_b, opts):
             "score_pass_s": round(t_score, 3), "start_pass_s": round(t_start, 3),
             "align_total_s": round(t_align, 3), "reconstruction_s": round(t_rec, 3),
             "score_pass_gcups": round(M * N / t_score / 1e9, 1)}
+
+
+def genome_leg(ctx, torch, swmi, synth):
+    """Score pass of the 32 Mbp x 28 Mbp genome-scale pair (letters resident on the device),
+    running-best pruning, row slabs of at most 1e14 cells (one launch each)."""
+    log("genome leg: generating the 32 Mbp x 28 Mbp pair")
+    p = synth.config5()
+    d_a, d_b = torch.from_numpy(p.a).cuda(), torch.from_numpy(p.b).cuda()
+    cells = p.cells
+    slabs = []
+    t0 = time.perf_counter()
+
+    def progress(done, total):
+        slabs.append(round(time.perf_counter() - t0, 2))
+        log(f"genome leg: {done}/{total} rows ({slabs[-1]:.1f} s)")
+
+    ws = ctx.workspace(ctx.workspace_size(p.a.size, p.b.size, prune=swmi.PRUNE_BEST))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.score_dev(d_a, d_b, workspace=ws, prune=swmi.PRUNE_BEST, progress=progress)
+    dt = time.perf_counter() - t0
+    del ws
+    return {"workload": "genome-scale pair: A 32 Mbp with GC-rich islands, B 28 Mbp from 40 shuffled, "
+                        "mutated pieces of A (4 reverse-complemented); forward strand, running-best pruning",
+            "cells": cells, "s": round(dt, 2), "gcups_eff": round(cells / dt / 1e9, 1),
+            "cells_computed_frac": round(r.cells_computed / cells, 4), "slab_ends_s": slabs,
+            "score": r.score, "end": [r.end_a, r.end_b]}
 
 
 def _pack(pairs):
@@ -358,58 +392,21 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
 
 
 def learned_leg(ctx, torch, swmi, synth, n_pairs):
-    """Learned threshold vs no pruning vs running-best pruning on 1-4 Mbp pairs."""
-    import numpy as np
+    """Learned threshold against no pruning, running-best pruning and the true score as
+    threshold (the ceiling), all batched, on a stratified draw of the 2 000-pair set."""
+    from paper_1304_5966_amd import eval_learned
     path = os.path.join(ROOT, "paper_1304_5966_amd", "models", "threshold_mlp.bin")
     if not os.path.exists(path) or n_pairs <= 0:
         return {"status": "no trained model in the tree"}
     model = swmi.Model(ctx, path)
-    log(f"learned leg: {n_pairs} pairs of 1-4 Mbp")
-    # a seeded subset of the evaluation seed's 2 000 pairs, homologous ones first
-    pairs = []
-    i = 0
-    while len(pairs) < n_pairs and i < 2000:
-        p = synth.config4_pair(i)
-        if p.homologous or len(pairs) >= n_pairs // 2:
-            pairs.append(p)
-        i += 1
-    a, oa, b, ob = _pack(pairs)
-    d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
-    cells = sum(p.cells for p in pairs)
-    out = {"workload": f"{len(pairs)} pairs of the 2 000-pair learned-pruning set (1-4 Mbp per side; "
-                       f"first homologous pairs of the evaluation seed, then the next pairs)",
-           "cells": cells}
-    ref = None
-    for name, kw in (("none", dict(prune=swmi.PRUNE_NONE)), ("best", dict(prune=swmi.PRUNE_BEST)),
-                     ("learned", dict(prune=swmi.PRUNE_LEARNED, model=model.handle))):
-        ws = ctx.workspace(ctx.batch_workspace_size(oa, ob, **kw))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = ctx.batch_dev(d_a, oa, d_b, ob, workspace=ws, **kw)
-        dt = time.perf_counter() - t0
-        keys = [r.key() for r in res]
-        if ref is None:
-            ref = keys
-        assert keys == ref, name
-        out[name] = {"gcups_eff": round(cells / dt / 1e9, 2), "s": round(dt, 3),
-                     "cells_computed_frac": round(sum(r.cells_computed for r in res) / cells, 4)}
-        if name == "learned":
-            out[name]["miss_rate"] = round(float(np.mean([r.fallback for r in res])), 4)
-        log(f"learned leg {name}: {cells / dt / 1e9:.1f} GCUPS")
-    # ceiling: threshold equal to the true score
-    best = [r[0] for r in ref]
-    t0 = time.perf_counter()
-    tot = 0
-    for k, p in enumerate(pairs):
-        r = ctx.score_dev(d_a[oa[k]:oa[k + 1]], d_b[ob[k]:ob[k + 1]], prune=swmi.PRUNE_LEARNED,
-                          threshold=max(best[k], 1))
-        assert r.key() == ref[k]
-        tot += r.cells_computed
-    dt = time.perf_counter() - t0
-    out["oracle_threshold"] = {"gcups_eff": round(cells / dt / 1e9, 2), "s": round(dt, 3),
-                               "cells_computed_frac": round(tot / cells, 4)}
-    out["speedup_learned_vs_none"] = round(out["none"]["s"] / out["learned"]["s"], 3)
+    idx = eval_learned.stratified_subset(n_pairs, seed=eval_learned.SUBSET_SEED + 1)
+    log(f"learned leg: {len(idx)} pairs of 1-4 Mbp")
+    part = eval_learned.evaluate(ctx, model, idx, chunk=len(idx), log=log)
     model.close()
+    out = eval_learned.summarize([part])
+    out["workload"] = (f"{len(idx)} pairs of the 2 000-pair learned-pruning set (1-4 Mbp per side), a seeded "
+                       f"draw keeping the set's mix ({part['homologous']} homologous); one batched launch per mode")
+    out["indices"] = idx
     return out
 
 

@@ -22,7 +22,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdlib>
+#include <deque>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -145,6 +148,7 @@ struct Piece {
     bool is_sub;
     Sub sub;
     Cigar ops;
+    Cigar* host = nullptr;  // handed to the host threads: their result (HostTail)
 };
 
 // Diagonal band [lo, hi] (j - i) holding every path of score >= S, or the full range.
@@ -281,6 +285,64 @@ struct HostMM {
     }
 };
 
+// The reconstruction's host part (paper Section 2: the CPU and the GPU work on the
+// reconstruction in parallel).  Sub-problems too small for a GPU level go to host
+// threads as soon as a level produces them, while the GPU runs the next levels.
+class HostTail {
+   public:
+    HostTail(const uint8_t* A, const uint8_t* B, int64_t g, int64_t h, int match, int mismatch, unsigned threads) {
+        for (unsigned t = 0; t < threads; ++t)
+            th_.emplace_back([=]() {
+                HostMM mm;
+                mm.A = A;
+                mm.B = B;
+                mm.g = g;
+                mm.h = h;
+                mm.match = match;
+                mm.mismatch = mismatch;
+                for (;;) {
+                    std::pair<Sub, Cigar*> job;
+                    {
+                        std::unique_lock<std::mutex> lk(mu_);
+                        cv_.wait(lk, [&] { return closed_ || !q_.empty(); });
+                        if (q_.empty()) return;
+                        job = q_.front();
+                        q_.pop_front();
+                    }
+                    const Sub& sb = job.first;
+                    mm.solve(A + sb.r0, sb.M, B + sb.c0, sb.N, sb.tb, sb.te, sb.score, sb.known, *job.second);
+                }
+            });
+    }
+    ~HostTail() { finish(); }
+    // Queues a sub-problem; its alignment will be in the returned Cigar once finish() returned.
+    Cigar* submit(const Sub& s) {
+        std::lock_guard<std::mutex> lk(mu_);
+        res_.emplace_back();
+        Cigar* c = &res_.back();  // deque elements keep their address
+        q_.emplace_back(s, c);
+        cv_.notify_one();
+        return c;
+    }
+    void finish() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            closed_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+        th_.clear();
+    }
+
+   private:
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<std::pair<Sub, Cigar*>> q_;
+    std::deque<Cigar> res_;
+    bool closed_ = false;
+    std::vector<std::thread> th_;
+};
+
 // Children of a sub-problem split at (j, type), with their exact scores.
 void split_sub(const Sub& s, const MidResult& r, int64_t g, int64_t h, std::vector<Piece>& out) {
     const int64_t mid = s.M / 2;
@@ -360,7 +422,8 @@ static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
     ScoreOut so;
     std::memcpy(&so, hm + 64, sizeof so);
-    if (so.score != score || so.status)
+    if (so.status) return fail(SW_EINTERNAL, "reverse pass: %s", engine_status_text(so.status));
+    if (so.score != score)
         return fail(SW_EINVAL, "no alignment of score %d ends at (%lld, %lld) (reverse pass reached %d)", score,
                     (long long)end_a, (long long)end_b, so.score);
     *start_a = end_a - so.end_a;
@@ -423,6 +486,17 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
     std::vector<Piece> pieces(1);
     pieces[0].is_sub = true;
     pieces[0].sub = Sub{0, M, 0, N, g, g, total_score, true};
+    // Host threads take the sub-problems below the GPU size as they appear.
+    const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    HostTail tail(hA.data(), hB.data(), g, h, sc->match, sc->mismatch, nthreads);
+    auto hand_small_to_host = [&]() {
+        for (auto& pc : pieces)
+            if (pc.is_sub && !(pc.sub.M >= kGpuRows && pc.sub.N > 0)) {
+                pc.host = tail.submit(pc.sub);
+                pc.is_sub = false;
+            }
+    };
+    hand_small_to_host();
     for (;;) {
         // GPU level over every sub-problem with enough rows.
         std::vector<size_t> big;
@@ -497,8 +571,11 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
         HIP_TRY(hipMemcpyAsync(d_mid, mids.data(), mids.size() * sizeof(MidTask), hipMemcpyHostToDevice, s));
         HIP_TRY(launch_midline(d_mid, (int64_t)mids.size(), oh, of, (int32_t)g, d_res, s));
         std::vector<MidResult> res(mids.size());
+        int32_t aborted = 0;
         HIP_TRY(hipMemcpyAsync(res.data(), d_res, mids.size() * sizeof(MidResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&aborted, eng + p.off_misc + MISC_ABORT, sizeof aborted, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (aborted) return fail(SW_EINTERNAL, "reconstruction: %s", engine_status_text(2));
         std::vector<Piece> next;
         next.reserve(pieces.size() + 2 * big.size());
         size_t k = 0;
@@ -515,38 +592,12 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
             }
         }
         pieces.swap(next);
+        hand_small_to_host();
     }
 
-    // Host threads finish the small sub-problems with the same rule.
-    std::vector<size_t> subs;
-    for (size_t i = 0; i < pieces.size(); ++i)
-        if (pieces[i].is_sub) subs.push_back(i);
-    std::atomic<size_t> next_sub{0};
-    const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    auto worker = [&]() {
-        HostMM mm;
-        mm.g = g;
-        mm.h = h;
-        mm.match = sc->match;
-        mm.mismatch = sc->mismatch;
-        for (;;) {
-            const size_t k = next_sub.fetch_add(1);
-            if (k >= subs.size()) break;
-            Piece& pc = pieces[subs[k]];
-            const Sub sb = pc.sub;
-            mm.A = hA.data();
-            mm.B = hB.data();
-            Cigar c;
-            mm.solve(hA.data() + sb.r0, sb.M, hB.data() + sb.c0, sb.N, sb.tb, sb.te, sb.score, sb.known, c);
-            pc.ops = std::move(c);
-            pc.is_sub = false;
-        }
-    };
-    std::vector<std::thread> th;
-    for (unsigned t = 1; t < nthreads && t < subs.size(); ++t) th.emplace_back(worker);
-    worker();
-    for (auto& t : th) t.join();
-    for (auto& pc : pieces) cigar.append(pc.ops);
+    // Every sub-problem is with the host threads now; the pieces in order make the CIGAR.
+    tail.finish();
+    for (auto& pc : pieces) cigar.append(pc.host ? *pc.host : pc.ops);
     return SW_OK;
 }
 

@@ -43,6 +43,11 @@ extern "C" const char* sw_version(void) { return "swmi 0.2 (gfx950)"; }
 
 size_t swmi::align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+const char* swmi::engine_status_text(int32_t status) {
+    return status == 2 ? "a stripe hand-off wait timed out (launch abandoned)"
+                       : "the endpoint of the best score was not tracked";
+}
+
 // ------------------------------------------------------------------------ fixed scratch
 
 // Workspace of sw_score_dev_noalloc: one fixed device array per GPU, held until
@@ -460,13 +465,14 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.top_h = top_h;
     a.top_f = top_f;
     a.jitter = schedule_jitter();
+    a.abort_flag = (int32_t*)(base + plan.off_misc + MISC_ABORT);
     for (const Prob& pr : plan.probs)
         if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))
             return fail(SW_EINTERNAL, "engine plan: a buffer top border without its row");
     const bool cd = sc->match + sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
-                          a.pruned, st));
+                          a.pruned, a.abort_flag, st));
     return SW_OK;
 }
 
@@ -606,7 +612,7 @@ static sw_status run_score_slabs(sw_context* ctx, const uint8_t* a_codes, int64_
         for (int i = 0; i < S; ++i) {
             const int s = (int)p.order[(size_t)i];  // probs[i] is strand order[i]
             const ScoreOut& r = so[i];
-            if (r.status) return fail(SW_EINTERNAL, "row slab %d: endpoint of the best score was not tracked", k);
+            if (r.status) return fail(SW_EINTERNAL, "row slab %d: %s", k, engine_status_text(r.status));
             pruned[s] += r.pruned_cells;
             if (r.end_a >= 0 && r.score > best[s]) {
                 best[s] = r.score;
@@ -676,7 +682,7 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
         if ((s = check_encoded(hm)) != SW_OK) return s;
         for (int i = 0; i < S; ++i) std::memcpy(&so[p.order[(size_t)i]], hm + 64 + i * sizeof(ScoreOut), sizeof(ScoreOut));
         for (int i = 0; i < S; ++i)
-            if (so[i].status) return fail(SW_EINTERNAL, "score pass: endpoint of the best score was not tracked");
+            if (so[i].status) return fail(SW_EINTERNAL, "score pass: %s", engine_status_text(so[i].status));
         report_progress(o, M, M);
     }
     // the better strand; the forward one on a tie

@@ -132,7 +132,7 @@ sw_status collect(const BatchLayout& L, const unsigned long long* flags, const S
     for (size_t k = 0; k < (size_t)L.plan.n_probs; ++k) {
         const size_t spec = (size_t)L.plan.order[k];
         const int32_t p = L.pair_of_spec[spec];
-        if (so[k].status) return fail(SW_EINTERNAL, "batch: endpoint of pair %d was not tracked", p);
+        if (so[k].status) return fail(SW_EINTERNAL, "batch, pair %d: %s", p, engine_status_text(so[k].status));
         sw_score_result& r = out[p];
         r.score = so[k].score;
         r.end_a = so[k].end_a;

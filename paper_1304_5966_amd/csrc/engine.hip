@@ -96,11 +96,38 @@ __device__ __forceinline__ void publish_count(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Bounded waits.  A wait that has not ended after kWaitLimit ticks of the 100 MHz
+// real-time counter raises the launch's abort flag; from then on every wait of the
+// launch ends at once, the kernel runs to completion on meaningless values and the
+// host reports an internal error instead of hanging.
+constexpr uint64_t kWaitLimit = 120ull * 100000000ull;  // 120 s
+
+// Called on every unsuccessful poll; true: give up waiting.
+__device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t& t0, uint32_t& polls) {
+    if (polls++ == 0) t0 = __builtin_amdgcn_s_memrealtime();
+    if ((polls & 255) != 0) return false;
+    if (load_count(abort_flag)) return true;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitLimit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return true;
+    }
+    return false;
+}
+
 // Waits until *flag >= need; `seen` caches the last value read.
-__device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need, int32_t& seen) {
+__device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need, int32_t& seen,
+                                              int32_t* abort_flag) {
+    uint64_t t0 = 0;
+    uint32_t polls = 0;
     while (seen < need) {
         seen = load_count(flag);
-        if (seen < need) __builtin_amdgcn_s_sleep(1);
+        if (seen < need) {
+            if (wait_abandoned(abort_flag, t0, polls)) {
+                seen = need;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
     }
     asm volatile("" ::: "memory");
 }
@@ -425,15 +452,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         // reader at all.
         if (task >= p.nslot) {
             int32_t seen = 0;
-            wait_at_least(p.progress + task - p.nslot, kDone, seen);
+            wait_at_least(p.progress + task - p.nslot, kDone, seen, p.abort_flag);
             if (tkt.reuse_reader >= 0) {
                 seen = 0;
-                wait_at_least(p.progress + tkt.reuse_reader, kDone, seen);
+                wait_at_least(p.progress + tkt.reuse_reader, kDone, seen, p.abort_flag);
             }
         }
         if (left_active) {
             int32_t seen = 0;
-            wait_at_least(p.progress + tkt.left, kDone, seen);
+            wait_at_least(p.progress + tkt.left, kDone, seen, p.abort_flag);
         }
 
         WaveState<R> s;
@@ -493,7 +520,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 return make_int2(h, LOCAL ? 0 : kNeg);
             }
             if (!prod_active) return make_int2(kNeg, kNeg);
-            wait_at_least(prod_prog, need, prod_seen);
+            wait_at_least(prod_prog, need, prod_seen, p.abort_flag);
             return ld_shared_i2(prod_slot + kSlotPad + rel);
         };
         {
@@ -502,7 +529,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 if (pr.top_kind == BORDER_BUF) h_diag = p.top_h[pr.top_off + c0];
                 else h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
             } else if (prod_active) {
-                wait_at_least(prod_prog, 1, prod_seen);
+                wait_at_least(prod_prog, 1, prod_seen, p.abort_flag);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
             } else if (band == 0) {
                 h_diag = border_h(pr.left_kind, pr.left_open, p.ext, R0);
@@ -510,7 +537,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 // H(R0 - 1, c0 - 1): the last column of the previous band, captured by
                 // the task above-left (no task of that stripe after it writes the row)
                 int32_t seen = 0;
-                wait_at_least(p.progress + tkt.corner, kDone, seen);
+                wait_at_least(p.progress + tkt.corner, kDone, seen, p.abort_flag);
                 h_diag = ld_shared_i2(lbuf + R0 - 1).x;
             } else {
                 h_diag = kNeg;
@@ -883,7 +910,8 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t words) {
 __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__ recs, const Prob* __restrict__ probs,
                                                      int64_t n_probs, int R, ScoreOut* out,
                                                      const unsigned long long* __restrict__ pruned,
-                                                     const int32_t* __restrict__ gbest) {
+                                                     const int32_t* __restrict__ gbest,
+                                                     const int32_t* __restrict__ abort_flag) {
     __shared__ int32_t s_v[256];
     __shared__ int64_t s_r[256];
     __shared__ int64_t s_c[256];
@@ -943,6 +971,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
                 if (pr.track && s_v[0] >= pr.target && (s_c[0] == INT64_MAX || s_c[0] >= pr.N || s_r[0] >= pr.M))
                     o.status = 1;
             }
+            if (abort_flag && *abort_flag) o.status = 2;
             out[pi] = o;
         }
         __syncthreads();
@@ -1002,10 +1031,11 @@ hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_pe
 }
 
 hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, int rows_per_lane, ScoreOut* out,
-                         const int32_t* gbest, const unsigned long long* pruned, hipStream_t st) {
+                         const int32_t* gbest, const unsigned long long* pruned, const int32_t* abort_flag,
+                         hipStream_t st) {
     const int blocks = (int)min((int64_t)4096, max((int64_t)1, n_probs));
     hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(256), 0, st, recs, probs, n_probs, rows_per_lane, out,
-                       pruned, gbest);
+                       pruned, gbest, abort_flag);
     return hipGetLastError();
 }
 

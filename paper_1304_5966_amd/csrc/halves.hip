@@ -179,7 +179,8 @@ sw_status swmi::run_score_halves(sw_context* ctx, const uint8_t* d_a, int64_t M,
     // plan_engine orders problems by size: probs[k] is spec order[k] (0 upper, 1 lower)
     const ScoreOut& up = so[p1.order[0] == 0 ? 0 : 1];
     const ScoreOut& lo = so[p1.order[0] == 0 ? 1 : 0];
-    if (up.status || lo.status) return fail(SW_EINTERNAL, "two-halves pass: a half's endpoint was not tracked");
+    if (up.status || lo.status)
+        return fail(SW_EINTERNAL, "two-halves pass: %s", engine_status_text(up.status ? up.status : lo.status));
     const int64_t S = std::max<int64_t>({(int64_t)up.score, (int64_t)lo.score, mr.value, 0});
     unsigned long long pruned = up.pruned_cells + lo.pruned_cells;
     unsigned long long cells = (unsigned long long)M * (unsigned long long)N;

@@ -78,10 +78,12 @@ struct EnginePlan {
 };
 
 // misc block (bytes from off_misc)
-enum { MISC_TICKET = 0, MISC_BAD_A = 16, MISC_BAD_B = 24, MISC_BYTES = 64 };
+enum { MISC_TICKET = 0, MISC_BAD_A = 16, MISC_BAD_B = 24, MISC_ABORT = 32, MISC_BYTES = 64 };
 constexpr unsigned long long kBadBase = 1ull << 62;
 
 size_t align_up(size_t v, size_t a);
+// ScoreOut::status as text.
+const char* engine_status_text(int32_t status);
 sw_status fail(sw_status st, const char* fmt, ...);
 sw_status ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out);
 sw_status check_scoring(const sw_scoring* s);

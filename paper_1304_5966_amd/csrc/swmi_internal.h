@@ -17,6 +17,7 @@ constexpr uint32_t kPadTable = 0x80808080u;
 constexpr int32_t kNeg = -(1 << 30);  // minus infinity of the global recurrence
 constexpr int64_t kNoBand = (int64_t)1 << 62;
 
+
 // Border of a problem's DP matrix (row 0 or column 0).
 enum BorderKind : int32_t {
     BORDER_ZERO = 0,  // local alignment: H = 0
@@ -110,11 +111,12 @@ struct EngineArgs {
     const int32_t* top_h;    // row 0 of BORDER_BUF problems: H
     const int32_t* top_f;    // and F (deletion-ending), as out_h/out_f write them
     uint32_t jitter;         // schedule-perturbation seed (tests; 0 = off)
+    int32_t* abort_flag;     // set when a wait timed out (cleared per launch)
 };
 
 struct ScoreOut {
     int32_t score;
-    int32_t status;          // 0 ok, else internal error code
+    int32_t status;          // 0 ok; 1 endpoint not tracked; 2 a wait of the launch timed out
     int64_t end_a, end_b;
     unsigned long long pruned_cells;
 };
@@ -153,7 +155,8 @@ hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_pe
                          hipStream_t st);
 // rows_per_lane: the launch's R (records of tasks outside a kept band are skipped).
 hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, int rows_per_lane, ScoreOut* out,
-                         const int32_t* gbest, const unsigned long long* pruned, hipStream_t st);
+                         const int32_t* gbest, const unsigned long long* pruned, const int32_t* abort_flag,
+                         hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t st);
 

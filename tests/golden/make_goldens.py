@@ -2,6 +2,7 @@
 
     python tests/golden/make_goldens.py config3 [--threads T]
     python tests/golden/make_goldens.py config2 [--threads T]
+    python tests/golden/make_goldens.py config4 --index I [--threads T]
 
 config3: score and endpoint of all 20 000 pairs of the batched workload
 (seed 13045969), each pair by the single-threaded linear-space oracle, pairs
@@ -11,6 +12,10 @@ config2: score, endpoint and start point of the 5 Mbp x 4 Mbp pair (seed
 13045968) by the multi-threaded linear-space oracle (row stripes on T
 threads; the start by the anchored reverse pass on the reversed prefixes) ->
 ``config2.json``.  About 3.5e13 cells: hours on a few cores.
+
+config4: score and endpoint of pair I of the learned-pruning evaluation set
+(1-4 Mbp per side; seed 13045971) by the multi-threaded linear-space oracle ->
+``config4_pair<I>.json``.
 
 Each file records the SHA-256 of the generated letters, so a test can tell a
 changed generator from a wrong result.  Nothing here touches the GPU library.
@@ -90,13 +95,33 @@ def config2(threads: int) -> None:
     os.replace(path + ".tmp", path)
 
 
+def config4(index: int, threads: int) -> None:
+    p = synth.config4_pair(index)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    path = os.path.join(HERE, f"config4_pair{index}.json")
+    t0 = time.time()
+    s, ea, eb = oracle.sw_score_mt(a, b, threads=threads)
+    rec = {"workload": f"pair {index} of the learned-pruning evaluation set (seed {synth.SEED_CONFIG4_EVAL}), "
+                       f"{len(a)} x {len(b)}, homologous segment: {p.homologous}",
+           "letters_sha256": letters_sha([p]), "scoring": list(oracle.SCORING), "threads": threads,
+           "score": s, "end_a": ea, "end_b": eb, "score_pass_s": round(time.time() - t0, 1)}
+    print(f"config4 pair {index}: score {s} end ({ea}, {eb}) in {time.time() - t0:.0f} s", flush=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(rec, f, indent=1)
+    os.replace(path + ".tmp", path)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=("config2", "config3"))
+    ap.add_argument("which", choices=("config2", "config3", "config4"))
     ap.add_argument("--threads", type=int, default=oracle.host_cores())
+    ap.add_argument("--index", type=int, default=581, help="config4: pair of the evaluation set")
     args = ap.parse_args()
     oracle.build()
-    (config2 if args.which == "config2" else config3)(args.threads)
+    if args.which == "config4":
+        config4(args.index, args.threads)
+    else:
+        (config2 if args.which == "config2" else config3)(args.threads)
 
 
 if __name__ == "__main__":

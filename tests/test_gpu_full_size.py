@@ -158,6 +158,31 @@ def test_config5_genome_scale_alignment(ctx, orc):
     _check_windows(a, b, al, orc, np.random.default_rng(5))
 
 
+def test_config4_pair_against_stored_oracle(ctx):
+    """A 1.06 Mbp x 1.01 Mbp pair of the learned-pruning evaluation set (pair 581, with a
+    homologous segment) in every pruning mode, against the oracle's stored score and endpoint."""
+    from paper_1304_5966_amd import swmi, train
+    path = os.path.join(GOLDEN, "config4_pair581.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle result not written")
+    with open(path) as f:
+        g = json.load(f)
+    p = synth.config4_pair(581)
+    assert g["letters_sha256"] == letters_sha([p]), "the pair generator changed"
+    exp = (g["score"], g["end_a"], g["end_b"])
+    a, b = p.a.tobytes(), p.b.tobytes()
+    modes = [dict(prune=swmi.PRUNE_NONE), dict(prune=swmi.PRUNE_BEST),
+             dict(prune=swmi.PRUNE_LEARNED, threshold=exp[0]), dict(prune=swmi.PRUNE_LEARNED, threshold=exp[0] + 1)]
+    model = swmi.Model(ctx, train.DEFAULT_OUT) if os.path.exists(train.DEFAULT_OUT) else None
+    if model:
+        modes.append(dict(prune=swmi.PRUNE_LEARNED, model=model.handle))
+    for kw in modes:
+        _case(f"config4 pair 581 {kw}")
+        assert ctx.score(a, b, **kw).key() == exp, kw
+    if model:
+        model.close()
+
+
 def test_config3_full_launch(ctx, orc):
     """All 20 000 pairs of the batch workload in one launch, in the shape the benchmark's tuner
     picks (6 rows per lane, 16 waves per CU): invariants on every pair, identical results under

@@ -208,3 +208,29 @@ def test_trained_model_on_evaluation_pairs(ctx):
           f"scores {[k[0] for k in ref]}", flush=True)
     assert frac["none"] == 1.0
     model.close()
+
+
+def test_trained_model_gain_on_stratified_full_size_pairs(ctx):
+    """What the network gains, at full size: ten pairs of the 2 000-pair evaluation set
+    (1-4 Mbp per side) drawn with the set's mix (four homologous, six unrelated), every mode
+    batched: no pruning, running-best pruning, the learned threshold and the true score as
+    threshold (the ceiling).  All modes return the same results; pruning never computes more
+    cells than the unpruned pass, the ceiling never more than running-best pruning; the learned
+    mode's cells and time against running-best pruning are reported either way (on the
+    200-pair stratified evaluation it loses to running-best pruning)."""
+    from paper_1304_5966_amd import eval_learned, swmi, train
+    if not os.path.exists(train.DEFAULT_OUT):
+        pytest.skip("no trained model in the tree")
+    model = swmi.Model(ctx, train.DEFAULT_OUT)
+    idx = eval_learned.stratified_subset(10, seed=eval_learned.SUBSET_SEED + 2)
+    _case(f"trained model on evaluation pairs {idx}")
+    part = eval_learned.evaluate(ctx, model, idx, chunk=10, log=lambda m: print(m, flush=True))
+    model.close()
+    res = eval_learned.summarize([part])
+    print({k: res[k] for k in ("none", "best", "learned", "ceiling", "misses", "thresholds_set",
+                               "speedup_learned_vs_best", "learned_beats_best")}, flush=True)
+    assert part["homologous"] == 4
+    assert res["none"]["cells_computed_frac"] == 1.0
+    assert res["best"]["cells_computed_frac"] <= 1.0
+    assert res["ceiling"]["cells_computed_frac"] <= res["best"]["cells_computed_frac"]
+    assert res["learned"]["cells_computed_frac"] <= 2.0  # a miss reruns its pair once
