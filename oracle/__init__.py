@@ -37,7 +37,34 @@ SCORING = (1, 3, 5, 2)  # match, mismatch penalty, gap open, gap extend (all con
 
 class _Scoring(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
-                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("matrix", ctypes.c_void_p), ("letter_class", ctypes.c_void_p),
+                ("size", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class MatrixScoring:
+    """Substitution-matrix scoring (protein alignment): s(x, y) = matrix[i][j] for the
+    letters alphabet[i], alphabet[j] (case-insensitive); gaps as in the tuple form.
+
+    Indexing like the tuple form: [0] the largest score, [2] gap open, [3] gap extend."""
+
+    def __init__(self, alphabet: bytes, matrix, gap_open: int, gap_extend: int):
+        self.alphabet = bytes(alphabet).upper()
+        self.matrix = np.ascontiguousarray(matrix, dtype=np.int8)
+        k = len(self.alphabet)
+        if self.matrix.shape != (k, k) or len(set(self.alphabet)) != k:
+            raise ValueError("matrix must be K x K for K distinct letters")
+        self.letter_class = np.full(256, -1, dtype=np.int8)
+        for i, c in enumerate(self.alphabet):
+            self.letter_class[c] = i
+            self.letter_class[ord(chr(c).lower())] = i
+        self.gap_open, self.gap_extend = int(gap_open), int(gap_extend)
+
+    def s(self, x: int, y: int) -> int:
+        return int(self.matrix[self.letter_class[x], self.letter_class[y]])
+
+    def __getitem__(self, i):
+        return (int(self.matrix.max()), 0, self.gap_open, self.gap_extend)[i]
 
 
 def build(force: bool = False) -> str:
@@ -89,7 +116,12 @@ def _bytes(x) -> bytes:
 
 
 def _sc(scoring) -> _Scoring:
-    return _Scoring(*[int(v) for v in scoring])
+    if isinstance(scoring, MatrixScoring):
+        sc = _Scoring(max(1, int(scoring.matrix.max())), 0, scoring.gap_open, scoring.gap_extend,
+                      scoring.matrix.ctypes.data, scoring.letter_class.ctypes.data, len(scoring.alphabet), 0)
+        sc._keep = scoring  # the arrays must outlive the call
+        return sc
+    return _Scoring(*[int(v) for v in scoring], None, None, 0, 0)
 
 
 def sw_score(a, b, scoring=SCORING, full: bool = False):
@@ -169,7 +201,7 @@ def mm_align(a, b, scoring=SCORING, tb: int = -1, te: int = -1) -> str:
 
 def global_score(a, b, scoring=SCORING, tb: int = -1, te: int = -1) -> int:
     a, b = _bytes(a), _bytes(b)
-    g = scoring[2] - scoring[3]
+    g = scoring[2] - scoring[3]  # gap open minus extend
     out = ctypes.c_int64()
     if lib().orc_global_score(a, len(a), b, len(b), ctypes.byref(_sc(scoring)),
                               g if tb < 0 else tb, g if te < 0 else te, ctypes.byref(out)):
@@ -214,7 +246,14 @@ def rescore(a, b, start_a, start_b, cigar: str, scoring=SCORING):
     Returns (score, end_a, end_b).  Each maximal I or D run costs open + extend*(k-1).
     """
     a, b = _bytes(a).upper(), _bytes(b).upper()
-    match, mismatch, go, ge = scoring
+    if isinstance(scoring, MatrixScoring):
+        subst = scoring.s
+        go, ge = scoring.gap_open, scoring.gap_extend
+    else:
+        match, mismatch, go, ge = scoring
+
+        def subst(x, y):
+            return match if x == y else -mismatch
     i, j, s = start_a, start_b, 0
     prev = None
     for n, o in parse_cigar(cigar):
@@ -223,7 +262,7 @@ def rescore(a, b, start_a, start_b, cigar: str, scoring=SCORING):
                 eq = a[i] == b[j]
                 if eq != (o == "="):
                     raise ValueError(f"CIGAR op {o} disagrees with letters at ({i},{j})")
-                s += match if eq else -mismatch
+                s += subst(a[i], b[j])
                 i += 1
                 j += 1
         else:

@@ -9,6 +9,8 @@ from __future__ import annotations
 
 
 def _s(x: int, y: int, sc) -> int:
+    if hasattr(sc, "s"):  # substitution matrix
+        return sc.s(x, y)
     return sc[0] if (x & 0xDF) == (y & 0xDF) else -sc[1]
 
 

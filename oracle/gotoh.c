@@ -11,7 +11,8 @@
  * What it computes (SW# paper, Section 2, and the affine-gap model stated in
  * its abstract):
  *   gap of length k costs   open + (k-1)*extend           (both positive)
- *   s(x,y) = +match if x == y (case-insensitive) else -mismatch
+ *   s(x,y) = +match if x == y (case-insensitive) else -mismatch, or an entry of a
+ *            substitution matrix over a given alphabet (protein scoring)
  *   E(i,j) = max(E(i,j-1) - extend, H(i,j-1) - open)     horizontal, consumes B  -> CIGAR 'I'
  *   F(i,j) = max(F(i-1,j) - extend, H(i-1,j) - open)     vertical,   consumes A  -> CIGAR 'D'
  *   H(i,j) = max(0, H(i-1,j-1) + s(A_i,B_j), E(i,j), F(i,j))
@@ -47,20 +48,41 @@ typedef struct {
     int32_t mismatch;   /* >= 0, subtracted on a mismatch */
     int32_t gap_open;   /* cost of the first gap position */
     int32_t gap_extend; /* cost of each further gap position */
+    /* Substitution matrix (protein scoring): NULL for the match/mismatch scoring
+     * above.  Otherwise letter_class maps every byte to its index in the alphabet
+     * (-1: not a letter of it) and s(x, y) = matrix[class(x) * size + class(y)]. */
+    const int8_t* matrix;
+    const int8_t* letter_class;
+    int32_t size;
+    int32_t pad_;
 } orc_scoring;
 
 static int up(uint8_t c) { return (c >= 'a' && c <= 'z') ? c - 32 : c; }
 
 static int64_t sub_score(uint8_t x, uint8_t y, const orc_scoring* sc) {
+    if (sc->matrix) return sc->matrix[sc->letter_class[x] * sc->size + sc->letter_class[y]];
     return up(x) == up(y) ? (int64_t)sc->match : -(int64_t)sc->mismatch;
 }
 
 static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
 
+static int bad_letters(const uint8_t* s, int64_t n, const orc_scoring* sc) {
+    if (!sc->matrix) return 0;
+    for (int64_t i = 0; i < n; i++)
+        if (sc->letter_class[s[i]] < 0) return 1;
+    return 0;
+}
+
 static int bad_args(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const orc_scoring* sc) {
     if (m < 0 || n < 0 || !sc) return 1;
     if ((m > 0 && !a) || (n > 0 && !b)) return 1;
-    if (sc->match <= 0 || sc->mismatch < 0 || sc->gap_extend <= 0 || sc->gap_open < sc->gap_extend) return 1;
+    if (sc->gap_extend <= 0 || sc->gap_open < sc->gap_extend) return 1;
+    if (sc->matrix) {
+        if (sc->size < 1 || sc->size > 32 || !sc->letter_class) return 1;
+        if (bad_letters(a, m, sc) || bad_letters(b, n, sc)) return 1;
+    } else if (sc->match <= 0 || sc->mismatch < 0) {
+        return 1;
+    }
     return 0;
 }
 
