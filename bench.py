@@ -11,8 +11,9 @@ flanks; scoring +1 / -3 / open 5 / extend 2, int32).  Prints one JSON line.
 Extra legs (reported in the same line, not in ``value``): the same pass with
 block pruning; the whole alignment of the pair (score pass, start pass,
 Myers-Miller reconstruction) timed by phase; the 20 000-pair batch; the
-learned threshold; and the CPU oracle timed on a bounded crop of the same pair.
-``--only batched|learned|align|genome`` runs one leg alone and prints its JSON
+learned threshold; substitution-matrix (protein) scoring; and the CPU oracle
+timed on a bounded crop of the same pair.
+``--only batched|learned|align|genome|protein`` runs one leg alone and prints its JSON
 (for profiling a leg by itself).  The genome leg is the score pass of the
 32 Mbp x 28 Mbp genome-scale pair with running-best pruning, in row slabs.
 """
@@ -134,7 +135,7 @@ def main():
                     help="only copy 1 GiB device-to-device (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--seq-sample", type=int, default=2000)
     ap.add_argument("--no-genome", action="store_true", help="skip the genome-scale leg (about 4.5 minutes)")
-    ap.add_argument("--only", choices=("batched", "learned", "align", "genome"), default=None,
+    ap.add_argument("--only", choices=("batched", "learned", "align", "genome", "protein"), default=None,
                     help="run one extra leg alone and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -157,6 +158,9 @@ def main():
     opts = dict(rows_per_lane=args.rows_per_lane, waves_per_cu=args.waves_per_cu)
     if args.only == "genome":
         print(json.dumps(genome_leg(swmi.Context(0), torch, swmi, synth)), flush=True)
+        return
+    if args.only == "protein":
+        print(json.dumps(protein_leg(swmi.Context(0), torch, swmi, synth)), flush=True)
         return
     if args.only in ("batched", "learned"):
         ctx = swmi.Context(0)
@@ -246,6 +250,7 @@ def main():
         line["alignment"] = alignment_leg(ctx, torch, pair, d_a, d_b, opts)
         line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)
         line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
+        line["protein"] = protein_leg(ctx, torch, swmi, synth)
         if not args.no_genome:
             line["genome_scale"] = genome_leg(ctx, torch, swmi, synth)
     if not args.no_cpu:
@@ -388,6 +393,53 @@ def batched_leg(ctx, torch, swmi, synth, seq_sample, tune):
     log(f"batched: {cells / dt / 1e9:.1f} GCUPS; per-pair calls: {sample_cells / dts / 1e9:.1f} GCUPS")
     out.update({"per_pair_calls_gcups": round(sample_cells / dts / 1e9, 2), "per_pair_sample": int(len(idx)),
                 "speedup_vs_per_pair": round((cells / dt) / (sample_cells / dts), 2)})
+    return out
+
+
+def protein_leg(ctx, torch, swmi, synth):
+    """Substitution-matrix scoring (protein): the engine reads its scores from a query profile
+    in LDS.  A 1 M x 1 M-letter pair (one launch) and a 20 000-pair batch, plain score pass,
+    seeded random 20-letter matrix in the usual protein value range, gaps 11 / 1."""
+    import numpy as np
+    sc = swmi.MatrixScoring(synth.AMINO, synth.substitution_matrix(synth.SEED_PROTEIN), 11, 1)
+    log("protein leg: 1 M x 1 M pair")
+    p = synth.protein_pair(synth.SEED_PROTEIN, 1_000_000, 1_000_000, 0.3)
+    d_a, d_b = torch.from_numpy(p.a).cuda(), torch.from_numpy(p.b).cuda()
+    ws = ctx.workspace(ctx.workspace_size(p.a.size, p.b.size))
+    r0 = ctx.score_dev(d_a, d_b, sc, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.score_dev(d_a, d_b, sc, workspace=ws)
+    dt = time.perf_counter() - t0
+    assert r.key() == r0.key()
+    # the same shape with DNA scoring (row tables instead of the profile), for reference
+    q = synth.homologous_pair(synth.SEED_PROTEIN, 1_000_000, 1_000_000, 0.3)
+    q_a, q_b = torch.from_numpy(q.a).cuda(), torch.from_numpy(q.b).cuda()
+    ctx.score_dev(q_a, q_b, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.score_dev(q_a, q_b, workspace=ws)
+    dt_dna = time.perf_counter() - t0
+    out = {"matrix": "seeded random 20 x 20, diagonal 4..11, off-diagonal -4..2; gap open 11, extend 1",
+           "pair": {"workload": "1 000 000 x 1 000 000 letters, B holding a mutated copy of A (divergence 30 %)",
+                    "gcups": round(p.cells / dt / 1e9, 1), "s": round(dt, 3), "score": r.score,
+                    "dna_same_shape_gcups": round(q.cells / dt_dna / 1e9, 1)}}
+    log("protein leg: 20 000-pair batch")
+    pairs = synth.protein_batch()
+    a, oa, b, ob = _pack(pairs)
+    d_a, d_b = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    cells = sum(q.cells for q in pairs)
+    ws = ctx.workspace(ctx.batch_workspace_size(oa, ob, sc))
+    first = ctx.batch_dev(d_a, oa, d_b, ob, sc, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.batch_dev(d_a, oa, d_b, ob, sc, workspace=ws)
+    dt = time.perf_counter() - t0
+    assert np.array_equal(res.array, first.array)
+    out["batch"] = {"workload": "20 000 pairs, lengths log-uniform 100-10 000 letters per side, even pairs "
+                                "homologous (divergence 10-60 %), odd pairs unrelated; one persistent launch",
+                    "cells": cells, "gcups": round(cells / dt / 1e9, 1), "ms": round(dt * 1000, 2)}
+    log(f"protein leg: pair {out['pair']['gcups']} GCUPS, batch {out['batch']['gcups']} GCUPS")
     return out
 
 

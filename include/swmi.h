@@ -15,8 +15,9 @@
  *   gap_open + (k - 1) * gap_extend.
  *
  * Conventions shared by every call:
- *  - Sequences are DNA letters "ACGTacgt" (case-insensitive).  Any other byte
- *    makes the call fail with SW_EINVAL and names the offset.
+ *  - Sequences are DNA letters "ACGTacgt" (case-insensitive), or with a
+ *    substitution matrix (sw_scoring.matrix) the letters of its alphabet.  Any
+ *    other byte makes the call fail with SW_EINVAL and names the offset.
  *  - A indexes rows (the reference), B indexes columns.
  *  - Coordinates are 0-based and inclusive.  When the best score is 0 the
  *    alignment is empty: start = end = -1 and the CIGAR is "".
@@ -25,7 +26,7 @@
  *    (start_a, start_b) from which that endpoint is reached with the best
  *    score; the alignment is the canonical Myers-Miller path (midline ties go
  *    to the smallest column, a plain crossing before a gap-spanning one).
- *  - CIGAR: run-length "=" (equal pair), "X" (unequal pair), "I" (consumes B
+ *  - CIGAR: run-length "=" (equal letters), "X" (unequal letters), "I" (consumes B
  *    only), "D" (consumes A only).
  *  - Host input buffers are borrowed read-only for the duration of the call;
  *    result structs are caller-owned (sw_align_result's CIGAR is freed with
@@ -53,16 +54,38 @@ typedef enum {
     SW_EINTERNAL = -5      /* internal consistency check failed */
 } sw_status;
 
+/* Substitution matrix (protein alignment: the library part behind the
+ * swsharpp executable that the paper's Section 3 lists beside the nucleotide
+ * ones; the paper gives no matrix): s(x, y) for a letter x of A
+ * and a letter y of B is scores[i * size + j] where alphabet[i] == x and
+ * alphabet[j] == y, letters compared case-insensitively.  The matrix need not
+ * be symmetric.  Requirements, else SW_EINVAL: 1 <= size <= 31 distinct
+ * letters (bytes 33..126, case-insensitively distinct), every score in
+ * -127..127.  Borrowed for the duration of the call. */
+typedef struct {
+    const char* alphabet;   /* size letters */
+    const int8_t* scores;   /* size x size, row = letter of A, column = letter of B */
+    int32_t size;
+    int32_t reserved;       /* 0 */
+} sw_matrix;
+
 /* Scoring (all configurations of the benchmark: 1, 3, 5, 2).
  * Requirements: 0 < match <= 127, 0 <= mismatch <= 127,
  * 0 < gap_extend <= gap_open, gap_open <= 2^20.  Otherwise SW_EINVAL.
+ * With a matrix, match and mismatch are ignored and the largest entry plays
+ * match's part in the bounds below (at least 1).
  * If match * min(len_a, len_b) >= 2^30 the call returns SW_EUNSUPPORTED
- * (int32 headroom). */
+ * (int32 headroom).
+ * Matrix scoring runs the same passes as DNA (score, start, alignment, batch,
+ * row slabs, two halves, external thresholds); not with a threshold model
+ * (SW_PRUNE_LEARNED without a threshold) or SW_FLAG_BOTH_STRANDS
+ * (SW_EUNSUPPORTED). */
 typedef struct {
-    int32_t match;       /* added for equal letters */
-    int32_t mismatch;    /* subtracted for unequal letters */
-    int32_t gap_open;    /* cost of a gap of length 1 */
-    int32_t gap_extend;  /* cost of each further gap position */
+    int32_t match;            /* added for equal letters */
+    int32_t mismatch;         /* subtracted for unequal letters */
+    int32_t gap_open;         /* cost of a gap of length 1 */
+    int32_t gap_extend;       /* cost of each further gap position */
+    const sw_matrix* matrix;  /* NULL: match / mismatch over ACGT */
 } sw_scoring;
 
 typedef enum {

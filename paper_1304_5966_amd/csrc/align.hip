@@ -168,14 +168,20 @@ void sub_band(const Sub& s, int match, int h, int64_t& lo, int64_t& hi) {
 // ------------------------------------------------------------------------ host Myers-Miller
 
 struct HostMM {
-    const uint8_t* A;  // codes of A' (0..3)
+    const uint8_t* A;  // codes of A' (DNA 0..3, or matrix classes)
     const uint8_t* B;  // codes of B'
     int64_t g, h;
-    int match, mismatch;
+    int match;         // largest substitution score (band bounds)
+    int32_t w_tab[kMaxClasses][kMaxClasses];  // s(x, y) by codes
     std::vector<int64_t> CC, DD, RR, SS;
     std::vector<uint8_t> ra, rb;
 
-    int64_t w(uint8_t x, uint8_t y) const { return x == y ? match : -(int64_t)mismatch; }
+    void set_scoring(const sw_scoring* sc) {
+        match = sc->match;
+        for (int x = 0; x < kMaxClasses; ++x)
+            for (int y = 0; y < kMaxClasses; ++y) w_tab[x][y] = subst_score(sc, (uint8_t)x, (uint8_t)y);
+    }
+    int64_t w(uint8_t x, uint8_t y) const { return w_tab[x][y]; }
     int64_t gap(int64_t k) const { return k > 0 ? g + h * k : 0; }
 
     // Forward over A[0..M) x B[0..N), columns outside [i + lo, i + hi] unreachable.
@@ -290,7 +296,7 @@ struct HostMM {
 // threads as soon as a level produces them, while the GPU runs the next levels.
 class HostTail {
    public:
-    HostTail(const uint8_t* A, const uint8_t* B, int64_t g, int64_t h, int match, int mismatch, unsigned threads) {
+    HostTail(const uint8_t* A, const uint8_t* B, int64_t g, int64_t h, const sw_scoring* sc, unsigned threads) {
         for (unsigned t = 0; t < threads; ++t)
             th_.emplace_back([=]() {
                 HostMM mm;
@@ -298,8 +304,7 @@ class HostTail {
                 mm.B = B;
                 mm.g = g;
                 mm.h = h;
-                mm.match = match;
-                mm.mismatch = mismatch;
+                mm.set_scoring(sc);
                 for (;;) {
                     std::pair<Sub, Cigar*> job;
                     {
@@ -407,9 +412,10 @@ static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     uint8_t* flags = (uint8_t*)ws + cb;
     uint8_t* eng = flags + 256;
     hipStream_t s = ctx->stream;
+    const EncTable et = enc_table(sc);
     HIP_TRY(launch_zero(flags, 256, s));
-    HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, 1, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_b, N, b_codes, kBPad, kBPadTail, 1, (unsigned long long*)(flags + 8), s));
+    HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, ENC_REVERSE, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_b, N, b_codes, kBPad, kBPadTail, ENC_REVERSE, et, (unsigned long long*)(flags + 8), s));
     if ((st = run_engine(ctx, p, a_codes, b_codes, sc, eng, nullptr, nullptr)) != SW_OK) return st;
     uint8_t* hm = (uint8_t*)ctx->host_misc;
     HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, s));
@@ -418,8 +424,8 @@ static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     unsigned long long bad_a, bad_b;
     std::memcpy(&bad_a, hm, 8);
     std::memcpy(&bad_b, hm + 8, 8);
-    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
-    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
+    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not %s", kBadBase - bad_a, letters_text(sc));
+    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not %s", kBadBase - bad_b, letters_text(sc));
     ScoreOut so;
     std::memcpy(&so, hm + 64, sizeof so);
     if (so.status) return fail(SW_EINTERNAL, "reverse pass: %s", engine_status_text(so.status));
@@ -436,8 +442,9 @@ extern "C" sw_status sw_start(sw_context* ctx, const char* a, int64_t len_a, con
                               int64_t* start_a, int64_t* start_b) {
     if (!ctx || !start_a || !start_b) return fail(SW_EINVAL, "sw_start: NULL argument");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
-    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, &sc)) != SW_OK) return st;
     if ((len_a && !a) || (len_b && !b)) return fail(SW_EINVAL, "sw_start: NULL sequence pointer");
     if (score <= 0) {
         *start_a = *start_b = -1;
@@ -451,7 +458,7 @@ extern "C" sw_status sw_start(sw_context* ctx, const char* a, int64_t len_a, con
     HIP_TRY(hipSetDevice(ctx->device));
     uint8_t *d_a, *d_b;
     if ((st = upload_pair(ctx, a, end_a + 1, b, end_b + 1, &d_a, &d_b)) != SW_OK) return st;
-    return start_pass(ctx, d_a, d_b, scoring, score, end_a, end_b, nullptr, start_a, start_b);
+    return start_pass(ctx, d_a, d_b, &sc, score, end_a, end_b, nullptr, start_a, start_b);
 }
 
 // ------------------------------------------------------------------------ reconstruction
@@ -473,11 +480,12 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
     uint8_t* rva = fb + lb;
     uint8_t* rvb = rva + la;
     uint8_t* flags = rvb + lb;
+    const EncTable et = enc_table(sc);
     HIP_TRY(launch_zero(flags, 256, s));
-    HIP_TRY(launch_encode(d_a, M, fa, 0, 64, 0, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_b, N, fb, kBPad, kBPadTail, 0, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_a, M, rva, 0, 64, 1, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_b, N, rvb, kBPad, kBPadTail, 1, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_a, M, fa, 0, 64, 0, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_b, N, fb, kBPad, kBPadTail, 0, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_a, M, rva, 0, 64, ENC_REVERSE, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_b, N, rvb, kBPad, kBPadTail, ENC_REVERSE, et, (unsigned long long*)flags, s));
     std::vector<uint8_t> hA((size_t)M), hB((size_t)N);
     HIP_TRY(hipMemcpyAsync(hA.data(), fa, (size_t)M, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hB.data(), fb + kBPad, (size_t)N, hipMemcpyDeviceToHost, s));
@@ -488,7 +496,7 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
     pieces[0].sub = Sub{0, M, 0, N, g, g, total_score, true};
     // Host threads take the sub-problems below the GPU size as they appear.
     const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    HostTail tail(hA.data(), hB.data(), g, h, sc->match, sc->mismatch, nthreads);
+    HostTail tail(hA.data(), hB.data(), g, h, sc, nthreads);
     auto hand_small_to_host = [&]() {
         for (auto& pc : pieces)
             if (pc.is_sub && !(pc.sub.M >= kGpuRows && pc.sub.N > 0)) {
@@ -604,6 +612,7 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
 // Score of a CIGAR placed at (0, 0) of A' x B' (codes), or a consistency failure.
 static bool rescore(const Cigar& c, const std::vector<uint8_t>& A, const std::vector<uint8_t>& B,
                     const sw_scoring* sc, int64_t& score, int64_t& ea, int64_t& eb) {
+    const EncTable et = enc_table(sc);
     int64_t i = 0, j = 0, s = 0;
     for (size_t k = 0; k < c.op.size(); ++k) {
         const char o = c.op[k];
@@ -611,9 +620,11 @@ static bool rescore(const Cigar& c, const std::vector<uint8_t>& A, const std::ve
         if (o == '=' || o == 'X') {
             for (int64_t t = 0; t < n; ++t, ++i, ++j) {
                 if (i >= (int64_t)A.size() || j >= (int64_t)B.size()) return false;
-                const bool eq = A[(size_t)i] == B[(size_t)j];
+                const uint8_t x = A[(size_t)i], y = B[(size_t)j];  // upper-case letters
+                const bool eq = x == y;
                 if (eq != (o == '=')) return false;
-                s += eq ? sc->match : -sc->mismatch;
+                if (et.dna) s += eq ? sc->match : -sc->mismatch;
+                else s += subst_score(sc, (uint8_t)et.cls[x], (uint8_t)et.cls[y]);
             }
         } else {
             s -= sc->gap_open + (int64_t)sc->gap_extend * (n - 1);
@@ -634,9 +645,11 @@ extern "C" sw_status sw_align(sw_context* ctx, const char* a, int64_t len_a, con
     out->start_a = out->start_b = out->end_a = out->end_b = -1;
     if (!ctx) return fail(SW_EINVAL, "sw_align: NULL context");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
-    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    sw_scoring nsc;
+    if ((st = check_scoring(scoring, &nsc)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, &nsc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&nsc, options)) != SW_OK) return st;
     if ((len_a && !a) || (len_b && !b)) return fail(SW_EINVAL, "sw_align: NULL sequence pointer");
     if ((int64_t)scoring->gap_open * (len_a + len_b + 2) >= ((int64_t)1 << 29))
         return fail(SW_EUNSUPPORTED, "gap_open * (len_a + len_b) reaches 2^29 (int32 headroom)");
@@ -664,18 +677,18 @@ extern "C" sw_status sw_align(sw_context* ctx, const char* a, int64_t len_a, con
     uint8_t *d_a, *d_b;
     if ((st = upload_pair(ctx, a, len_a, b, len_b, &d_a, &d_b)) != SW_OK) return st;
     int64_t sa, sb;
-    if ((st = start_pass(ctx, d_a, d_b, scoring, sr.score, sr.end_a, sr.end_b, options, &sa, &sb)) != SW_OK)
+    if ((st = start_pass(ctx, d_a, d_b, &nsc, sr.score, sr.end_a, sr.end_b, options, &sa, &sb)) != SW_OK)
         return st;
     Cigar cig;
     const int64_t M = sr.end_a - sa + 1, N = sr.end_b - sb + 1;
-    if ((st = reconstruct(ctx, d_a + sa, d_b + sb, M, N, scoring, sr.score, options, cig)) != SW_OK) return st;
+    if ((st = reconstruct(ctx, d_a + sa, d_b + sb, M, N, &nsc, sr.score, options, cig)) != SW_OK) return st;
     // consistency: the alignment must rescore to the best score and span the rectangle
     {
         std::vector<uint8_t> A((size_t)M), B((size_t)N);
         for (int64_t i = 0; i < M; ++i) A[(size_t)i] = (uint8_t)(a[sa + i] & 0xDF);
         for (int64_t j = 0; j < N; ++j) B[(size_t)j] = (uint8_t)(b[sb + j] & 0xDF);
         int64_t s2, ea, eb;
-        if (!rescore(cig, A, B, scoring, s2, ea, eb) || s2 != sr.score || ea != M - 1 || eb != N - 1)
+        if (!rescore(cig, A, B, &nsc, s2, ea, eb) || s2 != sr.score || ea != M - 1 || eb != N - 1)
             return fail(SW_EINTERNAL, "reconstruction does not rescore to the best score");
     }
     std::string text;
@@ -700,28 +713,32 @@ extern "C" sw_status sw_mm_host(const char* a, int64_t len_a, const char* b, int
                                 const sw_scoring* scoring, int32_t tb, int32_t te, int32_t score_known,
                                 int64_t score, char* cigar, int64_t cap, int64_t* cigar_len) {
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
     if (len_a < 0 || len_b < 0 || (len_a && !a) || (len_b && !b) || !cigar || cap <= 0 || !cigar_len)
         return fail(SW_EINVAL, "sw_mm_host: bad arguments");
+    const EncTable et = enc_table(&sc);
+    auto code_of = [&](char ch) -> int {
+        if (!et.dna) return et.cls[(uint8_t)ch];
+        const uint8_t u = (uint8_t)(ch & 0xDF);
+        return u == 'A' ? 0 : u == 'C' ? 1 : u == 'G' ? 2 : u == 'T' ? 3 : -1;
+    };
     std::vector<uint8_t> A((size_t)len_a), B((size_t)len_b);
     for (int64_t i = 0; i < len_a; ++i) {
-        const uint8_t ch = (uint8_t)(a[i] & 0xDF);
-        const int c = ch == 'A' ? 0 : ch == 'C' ? 1 : ch == 'G' ? 2 : ch == 'T' ? 3 : -1;
-        if (c < 0) return fail(SW_EINVAL, "sequence a: byte at offset %lld is not one of ACGTacgt", (long long)i);
+        const int c = code_of(a[i]);
+        if (c < 0) return fail(SW_EINVAL, "sequence a: byte at offset %lld is not %s", (long long)i, letters_text(&sc));
         A[(size_t)i] = (uint8_t)c;
     }
     for (int64_t j = 0; j < len_b; ++j) {
-        const uint8_t ch = (uint8_t)(b[j] & 0xDF);
-        const int c = ch == 'A' ? 0 : ch == 'C' ? 1 : ch == 'G' ? 2 : ch == 'T' ? 3 : -1;
-        if (c < 0) return fail(SW_EINVAL, "sequence b: byte at offset %lld is not one of ACGTacgt", (long long)j);
+        const int c = code_of(b[j]);
+        if (c < 0) return fail(SW_EINVAL, "sequence b: byte at offset %lld is not %s", (long long)j, letters_text(&sc));
         B[(size_t)j] = (uint8_t)c;
     }
-    const int64_t g = scoring->gap_open - scoring->gap_extend;
+    const int64_t g = sc.gap_open - sc.gap_extend;
     HostMM mm;
     mm.g = g;
-    mm.h = scoring->gap_extend;
-    mm.match = scoring->match;
-    mm.mismatch = scoring->mismatch;
+    mm.h = sc.gap_extend;
+    mm.set_scoring(&sc);
     mm.A = A.data();
     mm.B = B.data();
     Cigar c;

@@ -170,15 +170,95 @@ sw_status swmi::read_back(sw_context* ctx, const void* dev, size_t bytes, void**
 
 // ------------------------------------------------------------------------ checks
 
-sw_status swmi::check_scoring(const sw_scoring* s) {
+sw_status swmi::check_scoring(const sw_scoring* s, sw_scoring* norm) {
     if (!s) return fail(SW_EINVAL, "scoring is NULL");
-    if (s->match <= 0 || s->match > 127) return fail(SW_EINVAL, "match must be in 1..127 (got %d)", s->match);
-    if (s->mismatch < 0 || s->mismatch > 127)
-        return fail(SW_EINVAL, "mismatch must be in 0..127 (got %d)", s->mismatch);
     if (s->gap_extend <= 0 || s->gap_open < s->gap_extend || s->gap_open > (1 << 20))
         return fail(SW_EINVAL, "need 0 < gap_extend <= gap_open <= 2^20 (got %d, %d)", s->gap_open,
                     s->gap_extend);
+    *norm = *s;
+    if (!s->matrix) {
+        if (s->match <= 0 || s->match > 127) return fail(SW_EINVAL, "match must be in 1..127 (got %d)", s->match);
+        if (s->mismatch < 0 || s->mismatch > 127)
+            return fail(SW_EINVAL, "mismatch must be in 0..127 (got %d)", s->mismatch);
+        return SW_OK;
+    }
+    const sw_matrix* m = s->matrix;
+    if (m->size < 1 || m->size > kMaxClasses - 1)
+        return fail(SW_EINVAL, "matrix size must be in 1..%d (got %d)", kMaxClasses - 1, m->size);
+    if (!m->alphabet || !m->scores) return fail(SW_EINVAL, "matrix alphabet or scores is NULL");
+    bool seen[256] = {};
+    for (int i = 0; i < m->size; ++i) {
+        const uint8_t c = (uint8_t)m->alphabet[i];
+        const uint8_t u = (c >= 'a' && c <= 'z') ? (uint8_t)(c - 32) : c;
+        if (c < 33 || c > 126) return fail(SW_EINVAL, "matrix letter %d is not a printable byte (%d)", i, c);
+        if (seen[u]) return fail(SW_EINVAL, "matrix letter '%c' occurs twice (letters are case-insensitive)", c);
+        seen[u] = true;
+    }
+    int lo = 127, hi = -128;
+    for (int i = 0; i < m->size * m->size; ++i) {
+        const int v = m->scores[i];
+        if (v < -127) return fail(SW_EINVAL, "matrix score %d at %d is below -127", v, i);
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+    }
+    norm->match = std::max(1, hi);
+    norm->mismatch = std::max(0, -lo);
     return SW_OK;
+}
+
+sw_status swmi::check_matrix_options(const sw_scoring* sc, const sw_options* o) {
+    if (!sc->matrix || !o) return SW_OK;
+    if (o->prune_mode == SW_PRUNE_LEARNED && o->threshold == 0 && !o->pair_thresholds)
+        return fail(SW_EUNSUPPORTED, "a threshold model needs DNA scoring (its features are DNA k-mers); "
+                    "give the threshold instead");
+    if (o->flags & SW_FLAG_BOTH_STRANDS)
+        return fail(SW_EUNSUPPORTED, "SW_FLAG_BOTH_STRANDS needs DNA scoring (a reverse complement)");
+    return SW_OK;
+}
+
+static uint8_t upper(uint8_t c) { return (c >= 'a' && c <= 'z') ? (uint8_t)(c - 32) : c; }
+
+EncTable swmi::enc_table(const sw_scoring* sc) {
+    EncTable t;
+    std::memset(t.cls, -1, sizeof t.cls);
+    if (!sc->matrix) {
+        t.dna = 1;
+        t.pad_code = kPadCode;
+        return t;
+    }
+    const sw_matrix* m = sc->matrix;
+    t.dna = 0;
+    t.pad_code = m->size;  // the padding class follows the letters
+    for (int i = 0; i < m->size; ++i) {
+        const uint8_t u = upper((uint8_t)m->alphabet[i]);
+        t.cls[u] = (int8_t)i;
+        if (u >= 'A' && u <= 'Z') t.cls[u + 32] = (int8_t)i;
+    }
+    return t;
+}
+
+void swmi::subst_table(const sw_scoring* sc, Subst& out) {
+    std::memset(&out, 0, sizeof out);
+    if (!sc->matrix) return;
+    const sw_matrix* m = sc->matrix;
+    out.n_class = m->size + 1;
+    std::memset(out.s, -128, sizeof out.s);
+    for (int i = 0; i < m->size; ++i)
+        for (int j = 0; j < m->size; ++j) out.s[i][j] = m->scores[i * m->size + j];
+}
+
+int32_t swmi::subst_score(const sw_scoring* sc, uint8_t x, uint8_t y) {
+    if (!sc->matrix) {
+        if (x > 3 || y > 3) return -128;
+        return x == y ? sc->match : -sc->mismatch;
+    }
+    const int k = sc->matrix->size;
+    if (x >= k || y >= k) return -128;
+    return sc->matrix->scores[x * k + y];
+}
+
+const char* swmi::letters_text(const sw_scoring* sc) {
+    return sc->matrix ? "a letter of the matrix alphabet" : "one of ACGTacgt";
 }
 
 sw_status swmi::check_lengths(int64_t la, int64_t lb, const sw_scoring* s) {
@@ -466,6 +546,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.top_f = top_f;
     a.jitter = schedule_jitter();
     a.abort_flag = (int32_t*)(base + plan.off_misc + MISC_ABORT);
+    subst_table(sc, a.sub);
     for (const Prob& pr : plan.probs)
         if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))
             return fail(SW_EINTERNAL, "engine plan: a buffer top border without its row");
@@ -562,12 +643,12 @@ static void report_progress(const sw_options* o, int64_t done, int64_t total) {
 }
 
 // Bad-letter flags of the encode kernels, copied to the host.
-static sw_status check_encoded(const uint8_t* flags_host) {
+static sw_status check_encoded(const uint8_t* flags_host, const sw_scoring* sc) {
     unsigned long long bad_a, bad_b;
     std::memcpy(&bad_a, flags_host, 8);
     std::memcpy(&bad_b, flags_host + 8, 8);
-    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
-    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
+    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not %s", kBadBase - bad_a, letters_text(sc));
+    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not %s", kBadBase - bad_b, letters_text(sc));
     return SW_OK;
 }
 
@@ -656,11 +737,12 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
     uint8_t* rows = (uint8_t*)ws + cb;
     uint8_t* eng = rows + rows_bytes;
     hipStream_t st = ctx->stream;
+    const EncTable et = enc_table(sc);
     HIP_TRY(launch_zero(flags, 256, st));
-    HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, 0, (unsigned long long*)flags, st));
+    HIP_TRY(launch_encode(d_a, M, a_codes, 0, 64, 0, et, (unsigned long long*)flags, st));
     for (int s = 0; s < S; ++s)  // strand 1: the reverse complement of B
         HIP_TRY(launch_encode(d_b, N, b_codes + (size_t)s * b_code_bytes(N), kBPad, kBPadTail,
-                              s ? (ENC_REVERSE | ENC_COMPLEMENT) : 0, (unsigned long long*)(flags + 8), st));
+                              s ? (ENC_REVERSE | ENC_COMPLEMENT) : 0, et, (unsigned long long*)(flags + 8), st));
     uint8_t* hm = (uint8_t*)ctx->host_misc;
     ScoreOut so[2];
     sw_status s;
@@ -668,7 +750,7 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
         // letters first: a bad letter must not run a whole slab sequence
         HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if ((s = check_encoded(hm)) != SW_OK) return s;
+        if ((s = check_encoded(hm, sc)) != SW_OK) return s;
         if ((s = run_score_slabs(ctx, a_codes, M, b_codes, N, sc, o, h, S, rows, eng,
                                  ws_bytes - (size_t)(eng - (uint8_t*)ws), so)) != SW_OK)
             return s;
@@ -679,7 +761,7 @@ static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, 
         HIP_TRY(hipMemcpyAsync(hm, flags, 16, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(hm + 64, eng + p.off_outs, (size_t)S * sizeof(ScoreOut), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if ((s = check_encoded(hm)) != SW_OK) return s;
+        if ((s = check_encoded(hm, sc)) != SW_OK) return s;
         for (int i = 0; i < S; ++i) std::memcpy(&so[p.order[(size_t)i]], hm + 64 + i * sizeof(ScoreOut), sizeof(ScoreOut));
         for (int i = 0; i < S; ++i)
             if (so[i].status) return fail(SW_EINTERNAL, "score pass: %s", engine_status_text(so[i].status));
@@ -752,9 +834,11 @@ extern "C" sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t l
                                   void* d_workspace, size_t workspace_bytes, sw_score_result* out) {
     if (!ctx || !out) return fail(SW_EINVAL, "sw_score_dev: NULL context or result");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
-    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, &sc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&sc, options)) != SW_OK) return st;
     if ((len_a && !d_a) || (len_b && !d_b)) return fail(SW_EINVAL, "sw_score_dev: NULL sequence pointer");
     if (len_a == 0 || len_b == 0) {
         std::memset(out, 0, sizeof *out);
@@ -763,7 +847,7 @@ extern "C" sw_status sw_score_dev(sw_context* ctx, const uint8_t* d_a, int64_t l
     }
     if (!d_workspace) return fail(SW_EINVAL, "sw_score_dev: NULL workspace");
     HIP_TRY(hipSetDevice(ctx->device));
-    return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, d_workspace, workspace_bytes, out);
+    return run_score(ctx, d_a, len_a, d_b, len_b, &sc, options, d_workspace, workspace_bytes, out);
 }
 
 extern "C" sw_status sw_score_dev_noalloc(sw_context* ctx, const uint8_t* d_a, int64_t len_a, const uint8_t* d_b,
@@ -771,9 +855,11 @@ extern "C" sw_status sw_score_dev_noalloc(sw_context* ctx, const uint8_t* d_a, i
                                           sw_score_result* out) {
     if (!ctx || !out) return fail(SW_EINVAL, "sw_score_dev_noalloc: NULL context or result");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
-    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, &sc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&sc, options)) != SW_OK) return st;
     if ((len_a && !d_a) || (len_b && !d_b)) return fail(SW_EINVAL, "sw_score_dev_noalloc: NULL sequence pointer");
     if (len_a == 0 || len_b == 0) {
         std::memset(out, 0, sizeof *out);
@@ -787,7 +873,7 @@ extern "C" sw_status sw_score_dev_noalloc(sw_context* ctx, const uint8_t* d_a, i
     HIP_TRY(hipSetDevice(ctx->device));
     // Every intermediate the pass reads before writing (encode flags, counters,
     // running bests, records) is cleared by kernels inside run_score.
-    return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, ctx->scratch, SW_NOALLOC_SCRATCH_BYTES, out);
+    return run_score(ctx, d_a, len_a, d_b, len_b, &sc, options, ctx->scratch, SW_NOALLOC_SCRATCH_BYTES, out);
 }
 
 // Uploads host letters into the context's input buffer (checked on the device).
@@ -807,9 +893,11 @@ extern "C" sw_status sw_score(sw_context* ctx, const char* a, int64_t len_a, con
                               const sw_scoring* scoring, const sw_options* options, sw_score_result* out) {
     if (!ctx || !out) return fail(SW_EINVAL, "sw_score: NULL context or result");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
-    if ((st = check_lengths(len_a, len_b, scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
+    if ((st = check_lengths(len_a, len_b, &sc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&sc, options)) != SW_OK) return st;
     if ((len_a && !a) || (len_b && !b)) return fail(SW_EINVAL, "sw_score: NULL sequence pointer");
     if (len_a == 0 || len_b == 0) {
         std::memset(out, 0, sizeof *out);
@@ -822,5 +910,5 @@ extern "C" sw_status sw_score(sw_context* ctx, const char* a, int64_t len_a, con
     const size_t need = score_workspace_size(ctx, len_a, len_b, options);
     void* ws;
     if ((st = ctx_buffer(ctx, BUF_WORK, need, &ws)) != SW_OK) return st;
-    return run_score(ctx, d_a, len_a, d_b, len_b, scoring, options, ws, need, out);
+    return run_score(ctx, d_a, len_a, d_b, len_b, &sc, options, ws, need, out);
 }

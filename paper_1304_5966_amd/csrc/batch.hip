@@ -100,11 +100,13 @@ sw_status batch_device_work(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     hipStream_t s = ctx->stream;
     int64_t* tab = (int64_t*)(base + L.off_tab);
     unsigned long long* bad = (unsigned long long*)(base + L.off_flags);
+    const EncTable et = enc_table(sc);
+    const int32_t pad4 = (int32_t)(0x01010101u * (uint32_t)et.pad_code);  // padding code in every byte
     HIP_TRY(launch_zero(base + L.off_flags, 256, s));
-    HIP_TRY(launch_fill_i32((int32_t*)(base + L.off_b), 0x04040404, (size_t)(L.b_bytes + 64 + 3) / 4, s));
-    HIP_TRY(launch_encode_many(d_a, tab, tab + n, tab + 2 * (size_t)n, n, base + L.off_a, bad, s));
+    HIP_TRY(launch_fill_i32((int32_t*)(base + L.off_b), pad4, (size_t)(L.b_bytes + 64 + 3) / 4, s));
+    HIP_TRY(launch_encode_many(d_a, tab, tab + n, tab + 2 * (size_t)n, n, base + L.off_a, et, bad, s));
     HIP_TRY(launch_encode_many(d_b, tab + 3 * (size_t)n, tab + 4 * (size_t)n, tab + 5 * (size_t)n, n,
-                               base + L.off_b, bad + 1, s));
+                               base + L.off_b, et, bad + 1, s));
     return launch_engine_kernels(ctx, L.plan, base + L.off_a, base + L.off_b, sc, base + L.off_eng, nullptr, nullptr);
 }
 
@@ -126,9 +128,10 @@ void clear_out(sw_score_result* out, int32_t n) {
 }
 
 // Per-pair results from the launch's bad-letter flags and per-problem outputs.
-sw_status collect(const BatchLayout& L, const unsigned long long* flags, const ScoreOut* so, sw_score_result* out) {
-    if (flags[0]) return fail(SW_EINVAL, "seqs_a: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[0]);
-    if (flags[1]) return fail(SW_EINVAL, "seqs_b: byte at offset %llu is not one of ACGTacgt", kBadBase - flags[1]);
+sw_status collect(const BatchLayout& L, const unsigned long long* flags, const ScoreOut* so, const sw_scoring* sc,
+                  sw_score_result* out) {
+    if (flags[0]) return fail(SW_EINVAL, "seqs_a: byte at offset %llu is not %s", kBadBase - flags[0], letters_text(sc));
+    if (flags[1]) return fail(SW_EINVAL, "seqs_b: byte at offset %llu is not %s", kBadBase - flags[1], letters_text(sc));
     for (size_t k = 0; k < (size_t)L.plan.n_probs; ++k) {
         const size_t spec = (size_t)L.plan.order[k];
         const int32_t p = L.pair_of_spec[spec];
@@ -163,7 +166,7 @@ sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int
     HIP_TRY(hipMemcpyAsync(so.data(), base + L.off_eng + L.plan.off_outs, so.size() * sizeof(ScoreOut),
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return collect(L, flags, so.data(), out);
+    return collect(L, flags, so.data(), sc, out);
 }
 
 // A captured batch: the graph copies the tables from pinned host memory owned
@@ -198,6 +201,12 @@ uint64_t inputs_key(const sw_context* ctx, const uint8_t* d_a, const uint8_t* d_
                        (uint64_t)o->band_width, (uint64_t)o->flags})
         key = mix(key, v);
     for (int c = 0; c < 4; ++c) key = mix(mix(key, (uint64_t)ctx->tuned_R[c]), (uint64_t)ctx->tuned_wpc[c]);
+    if (sc->matrix) {  // the matrix content (a replay bakes its table into the launch)
+        const sw_matrix* m = sc->matrix;
+        key = mix(key, (uint64_t)m->size);
+        for (int i = 0; i < m->size; ++i) key = mix(key, (uint64_t)(uint8_t)m->alphabet[i]);
+        for (int i = 0; i < m->size * m->size; ++i) key = mix(key, (uint64_t)(uint8_t)m->scores[i]);
+    }
     for (size_t i = 0; i < as.size(); ++i)
         key = mix(mix(mix(mix(key, (uint64_t)as[i]), (uint64_t)al[i]), (uint64_t)bs[i]), (uint64_t)bl[i]);
     for (int32_t t : T) key = mix(key, (uint64_t)(uint32_t)t);
@@ -275,7 +284,7 @@ sw_status run_batch_graph(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_
     HIP_TRY(hipMemcpyAsync(hp + g->off_outs, base + L.off_eng + L.plan.off_outs,
                            (size_t)L.plan.n_probs * sizeof(ScoreOut), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return collect(L, (const unsigned long long*)(hp + g->off_flags), (const ScoreOut*)(hp + g->off_outs), out);
+    return collect(L, (const unsigned long long*)(hp + g->off_flags), (const ScoreOut*)(hp + g->off_outs), sc, out);
 }
 
 }  // namespace
@@ -302,10 +311,12 @@ static bool batch_uses_model(const sw_options* o) {
 extern "C" size_t sw_batch_workspace_size(sw_context* ctx, const int64_t* offs_a, const int64_t* offs_b,
                                           int32_t n_pairs, const sw_scoring* scoring, const sw_options* options) {
     if (!ctx || !scoring) return 0;
+    sw_scoring sc;
+    if (check_scoring(scoring, &sc) != SW_OK) return 0;
     std::vector<int64_t> as, al, bs, bl;
     if (pairs_of(offs_a, offs_b, n_pairs, as, al, bs, bl) != SW_OK) return 0;
     BatchLayout L;
-    if (make_layout(ctx, as, al, bs, bl, scoring, options, nullptr, L) != SW_OK) return 0;
+    if (make_layout(ctx, as, al, bs, bl, &sc, options, nullptr, L) != SW_OK) return 0;
     size_t total = L.total;
     if (batch_uses_model(options)) {
         int64_t mM = 0, mN = 0;
@@ -416,8 +427,10 @@ extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, cons
                                   size_t workspace_bytes, sw_score_result* out) {
     if (!ctx || (n_pairs > 0 && !out)) return fail(SW_EINVAL, "sw_batch_dev: NULL context or results");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&sc, options)) != SW_OK) return st;
     if (options && (options->flags & (SW_FLAG_HALVES | SW_FLAG_BOTH_STRANDS)))
         return fail(SW_EUNSUPPORTED, "sw_batch: SW_FLAG_HALVES and SW_FLAG_BOTH_STRANDS are single-pair options");
     std::vector<int64_t> as, al, bs, bl;
@@ -425,7 +438,7 @@ extern "C" sw_status sw_batch_dev(sw_context* ctx, const uint8_t* d_seqs_a, cons
     if (n_pairs > 0 && (!d_seqs_a || !d_seqs_b)) return fail(SW_EINVAL, "sw_batch_dev: NULL sequences");
     if (n_pairs > 0 && !d_workspace) return fail(SW_EINVAL, "sw_batch_dev: NULL workspace");
     HIP_TRY(hipSetDevice(ctx->device));
-    return batch_all(ctx, d_seqs_a, d_seqs_b, as, al, bs, bl, scoring, options, d_workspace, workspace_bytes, out);
+    return batch_all(ctx, d_seqs_a, d_seqs_b, as, al, bs, bl, &sc, options, d_workspace, workspace_bytes, out);
 }
 
 extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t* offs_a, const char* seqs_b,
@@ -433,8 +446,10 @@ extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t
                               const sw_options* options, sw_score_result* out) {
     if (!ctx || (n_pairs > 0 && !out)) return fail(SW_EINVAL, "sw_batch: NULL context or results");
     sw_status st;
-    if ((st = check_scoring(scoring)) != SW_OK) return st;
+    sw_scoring sc;
+    if ((st = check_scoring(scoring, &sc)) != SW_OK) return st;
     if ((st = check_options(options)) != SW_OK) return st;
+    if ((st = check_matrix_options(&sc, options)) != SW_OK) return st;
     if (options && (options->flags & (SW_FLAG_HALVES | SW_FLAG_BOTH_STRANDS)))
         return fail(SW_EUNSUPPORTED, "sw_batch: SW_FLAG_HALVES and SW_FLAG_BOTH_STRANDS are single-pair options");
     std::vector<int64_t> as, al, bs, bl;
@@ -457,5 +472,5 @@ extern "C" sw_status sw_batch(sw_context* ctx, const char* seqs_a, const int64_t
     if (!need) return fail(SW_EINTERNAL, "sw_batch: workspace size");
     void* ws;
     if ((st = ctx_buffer(ctx, BUF_WORK, need, &ws)) != SW_OK) return st;
-    return batch_all(ctx, d_a, d_b, as, al, bs, bl, scoring, options, ws, need, out);
+    return batch_all(ctx, d_a, d_b, as, al, bs, bl, &sc, options, ws, need, out);
 }

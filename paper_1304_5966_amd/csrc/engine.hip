@@ -22,7 +22,10 @@
 //    from an LDS staging ring.
 //  * Substitution scores: per row a 4-byte table s(a_row, c), c = 0..3; one
 //    v_perm_b32 with four column codes as selector yields four score bytes,
-//    consumed by sign-extended byte-select adds.
+//    consumed by sign-extended byte-select adds.  With a substitution matrix
+//    (protein) the stripe keeps a query profile in LDS instead: for every
+//    letter class c, the lane's R row scores s(a_row, c) as bytes; one LDS read
+//    per step at the column's class yields the step's R score bytes.
 //  * Columns are cut into bands of W; a task is (problem, band, stripe), taken
 //    from an in-order ticket counter through a host-built table (problems in
 //    decreasing size; the tasks of a group of problems interleaved, each
@@ -186,6 +189,7 @@ struct TickCtx {
     const int2* in_cd;    // the same inputs plus m * ext (column-shifted domain, step m)
     int2* out;            // LDS: 64 lane-63 outputs
     const uint32_t* bring;  // LDS: the tick's column codes, dwords from bbase on (shifted ticks)
+    const uint32_t* prof;   // LDS: this lane's query-profile entry of class 0 (matrix scoring)
     uintptr_t bbase;        // address of the first staged dword
     int2* lbuf;           // right-boundary store for the next band (capture)
     int32_t* out_h;       // last-row outputs (reconstruction halves)
@@ -202,6 +206,44 @@ struct TickCtx {
     bool capture;         // store H,E at the band's last column into lbuf
 };
 
+// Substitution scores of one group of 4 steps for the lane's R rows.
+//  DNA:    per row one v_perm_b32 of the row's 4-entry table by the four column
+//          codes (pad code 4 selects a byte of kPadTable).
+//  matrix: per step one LDS read of the query profile at the step's column
+//          class: entry (class, lane) holds the R row scores as bytes, so the
+//          read is 4 or 8 bytes at (class * 64 + lane) * (4 or 8) -- bank-conflict
+//          free within each half wave.
+template <int R, bool PROT>
+struct ScoreGroup {
+    uint32_t sc[R];
+    __device__ __forceinline__ void load(const uint32_t (&T)[R], uint32_t cw, const TickCtx&) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, T[k], cw);
+    }
+    __device__ __forceinline__ int get(int i, int k) const { return sext_byte(sc[k], i); }
+};
+
+template <int R>
+struct ScoreGroup<R, true> {
+    static constexpr int kW = R > 4 ? 2 : 1;  // dwords per profile entry
+    uint32_t w[4][kW];
+    __device__ __forceinline__ void load(const uint32_t (&)[R], uint32_t cw, const TickCtx& c) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t cls = __builtin_amdgcn_ubfe(cw, 8 * i, 8);
+            const uint32_t* e = c.prof + cls * (uint32_t)(kWave * kW);
+            if (kW == 2) {
+                const uint2 v = *reinterpret_cast<const uint2*>(e);
+                w[i][0] = v.x;
+                w[i][kW - 1] = v.y;
+            } else {
+                w[i][0] = *e;
+            }
+        }
+    }
+    __device__ __forceinline__ int get(int i, int k) const { return sext_byte(w[i][k >> 2], k & 3); }
+};
+
 // Tick modes.
 //  kRun:   compute; per-row running maxima.
 //  kTrack: replay -- no outputs, no maxima; records the first column where a
@@ -214,13 +256,20 @@ constexpr int kRun = 0, kTrack = 1, kExact = 2;
 //        their state (tick 0); H,E at the band's last column go to lbuf; the
 //        last matrix row's H and F go to out_h/out_f.
 //  CD:   the row tables hold s + ext (the shifted-domain tables); subtract it.
-template <int R, bool LOCAL, int MODE, bool SLOW, bool CD>
+template <int R, bool LOCAL, int MODE, bool SLOW, bool CD, bool PROT>
 __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const uint8_t* first,
                                          const TickCtx& c, const bool (&want)[R]) {
     constexpr bool REPLAY = MODE != kRun;
     const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)first & ~(uintptr_t)3);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
     uint32_t lo = src[0], hi = src[1];
+    // Matrix scoring: the profile reads of a group are issued one group ahead, and
+    // the column-code dwords that address them one group before that (LDS reads
+    // complete in order, so a code dword read just before its use would also wait
+    // for the profile reads in flight).
+    uint32_t hi2 = PROT ? src[2] : 0;
+    ScoreGroup<R, PROT> sg_next;
+    if (PROT) sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
     // lane 0's inputs are read one 4-step group ahead (the ring holds 64 + 4 entries)
     const int4* in4 = reinterpret_cast<const int4*>(c.in);
     int4 nx0 = in4[0], nx1 = in4[1];
@@ -230,14 +279,23 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
     for (int g = 0; g < kTick / 4; ++g) {
         const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
         lo = hi;
-        hi = src[g + 2];
+        if (PROT) {
+            hi = hi2;
+            hi2 = src[g + 3];
+        } else {
+            hi = src[g + 2];
+        }
         const int2 ins[4] = {make_int2(nx0.x, nx0.y), make_int2(nx0.z, nx0.w), make_int2(nx1.x, nx1.y),
                              make_int2(nx1.z, nx1.w)};
         nx0 = in4[2 * g + 2];
         nx1 = in4[2 * g + 3];
-        uint32_t sc[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, s.T[k], cw);
+        ScoreGroup<R, PROT> sg;
+        if (PROT) {
+            sg = sg_next;
+            sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
+        } else {
+            sg.load(s.T, cw, c);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = 4 * g + i;
@@ -251,7 +309,7 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
             const bool act = SLOW ? (rel >= 0) : true;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const int Hd = diag + sext_byte(sc[k], i) - bias;
+                const int Hd = diag + sg.get(i, k) - bias;
                 const int En = LOCAL ? max(max(s.E[k] - c.ext, s.HA[k]), 0) : max(s.E[k] - c.ext, s.HA[k]);
                 const int Hn = max(max(Hd, En), F);
                 const int HAn = Hn - c.open;
@@ -310,7 +368,7 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
 //
 // TRACKMAX = false: no running maximum (returns kNeg), for ticks whose cells
 // provably stay below the value that would need it.
-template <int R, bool TRACKMAX, bool LOCAL>
+template <int R, bool TRACKMAX, bool LOCAL, bool PROT>
 __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
     const int ext = c.ext, g = c.open - c.ext;
     const int off = -(c.lane + 1) * ext;  // the carried state belongs to step -1
@@ -333,18 +391,31 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     uint32_t lo = src[0], hi = src[1];
     const int4* in4 = reinterpret_cast<const int4*>(c.in_cd);
     int4 nx0 = in4[0], nx1 = in4[1];
+    // matrix scoring: profile reads one group ahead, their code dwords two (see run_tick)
+    uint32_t hi2 = PROT ? src[2] : 0;
+    ScoreGroup<R, PROT> sg_next;
+    if (PROT) sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
 #pragma unroll 2
     for (int gi = 0; gi < kTick / 4; ++gi) {
         const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
         lo = hi;
-        hi = src[gi + 2];
+        if (PROT) {
+            hi = hi2;
+            hi2 = src[gi + 3];
+        } else {
+            hi = src[gi + 2];
+        }
         const int2 ins[4] = {make_int2(nx0.x, nx0.y), make_int2(nx0.z, nx0.w), make_int2(nx1.x, nx1.y),
                              make_int2(nx1.z, nx1.w)};
         nx0 = in4[2 * gi + 2];
         nx1 = in4[2 * gi + 3];
-        uint32_t sc[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) sc[k] = __builtin_amdgcn_perm(kPadTable, s.T[k], cw);
+        ScoreGroup<R, PROT> sg;
+        if (PROT) {
+            sg = sg_next;
+            sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
+        } else {
+            sg.load(s.T, cw, c);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = 4 * gi + i;
@@ -356,7 +427,7 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
             if (TRACKMAX) acc += ext;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const int Hd = diag + sext_byte(sc[k], i);
+                const int Hd = diag + sg.get(i, k);
                 const int En = LOCAL ? max(max(s.E[k], HA[k]), z) : max(s.E[k], HA[k]);
                 const int Hn = max(max(Hd, En), F);
                 const int HAn = Hn - g;
@@ -396,12 +467,15 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
 // match + ext <= 127 so that s + ext fits the score bytes.
 // OCC: resident waves per SIMD the register allocation is sized for
 // (512 / OCC VGPRs per lane).
-template <int R, bool LOCAL, bool CD, int OCC>
+// PROT: matrix scoring; the query profile takes p.sub.n_class * 64 * (4 or 8)
+// bytes of dynamic LDS.
+template <int R, bool LOCAL, bool CD, int OCC, bool PROT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void engine_kernel(EngineArgs p) {
     __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
     __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
-    // Column codes of a tick: lane l reads from column col0 - l on, 18 dwords; the
-    // union over lanes is kBring dwords from the dword holding column col0 - 63.
+    // Column codes of a tick: lane l reads from column col0 - l on, 18 dwords (19
+    // with matrix scoring, at most index 34); the union over lanes is kBring dwords
+    // from the dword holding column col0 - 63.
     constexpr int kBring = 36;
     __shared__ uint32_t b_ring[CD ? 2 : 1][kBring];
     // Row maxima and the pre-tick snapshot live in LDS (one column per lane) so
@@ -409,6 +483,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     __shared__ int lds_best[R][kWave], lds_pos[R][kWave];
     __shared__ int lds_snap[2 * R + 3][kWave];
     __shared__ __attribute__((aligned(16))) int2 out_buf[kTick];
+    // Query profile (matrix scoring): entry (class c, lane l) at dword (c * 64 + l) * kPW
+    // holds s(row, c) + bias for the R rows of lane l, one byte per row (-128 for
+    // rows past the matrix and for the padding class).
+    extern __shared__ __attribute__((aligned(16))) uint32_t prof_lds[];
+    constexpr int kPW = R > 4 ? 2 : 1;
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
     const int lane = threadIdx.x;
 
@@ -468,7 +547,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int64_t row = row0 + k;
-            int code = kPadCode;
+            int code = PROT ? 0xff : kPadCode;  // rows past the matrix score -128
             int h = NEGV, e = NEGV;
             if (row < pr.M) {
                 code = acodes[row];
@@ -483,12 +562,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     e = kNeg;
                 }
             }
-            s.T[k] = row_table(code, p.match, p.mismatch, CD ? p.ext : 0);
+            s.T[k] = PROT ? (uint32_t)code : row_table(code, p.match, p.mismatch, CD ? p.ext : 0);
             s.H[k] = h;
             s.E[k] = e;
             s.HA[k] = h - p.open;
             lds_best[k][lane] = LOCAL ? 0 : kNeg;
             lds_pos[k][lane] = -1;
+        }
+        if (PROT) {
+            // This task's query profile.  Each lane writes and later reads only its
+            // own entries, so no barrier is needed; the row codes were parked in T.
+            const int nc = p.sub.n_class;
+            const int bias = CD ? p.ext : 0;
+            for (int cl = 0; cl < nc; ++cl) {
+                uint32_t w[kPW];
+#pragma unroll
+                for (int d = 0; d < kPW; ++d) w[d] = 0;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const uint32_t rc = s.T[k];
+                    const int sv = p.sub.s[min(rc, (uint32_t)(kMaxClasses - 1))][cl];
+                    const int v = (rc >= (uint32_t)(nc - 1) || cl == nc - 1) ? -128 : sv + bias;
+                    w[k >> 2] |= (uint32_t)(uint8_t)(int8_t)v << (8 * (k & 3));
+                }
+                uint32_t* e = prof_lds + ((uint32_t)cl * kWave + (uint32_t)lane) * kPW;
+                if (kPW == 2) *reinterpret_cast<uint2*>(e) = make_uint2(w[0], w[kPW - 1]);
+                else e[0] = w[0];
+            }
         }
         s.hup = 0;
         s.hl = s.H[R - 1];
@@ -553,6 +653,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         __syncthreads();
 
         TickCtx c;
+        c.prof = prof_lds + (uint32_t)lane * kPW;
         c.out = out_buf;
         c.lbuf = lbuf;
         c.out_h = p.out_h;
@@ -732,8 +833,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
                 if (track_max) snapshot();  // without the running maximum there is no replay
-                const int tmax = track_max ? run_tick_cd<R, true, LOCAL>(s, cols, c)
-                                           : run_tick_cd<R, false, LOCAL>(s, cols, c);
+                const int tmax = track_max ? run_tick_cd<R, true, LOCAL, PROT>(s, cols, c)
+                                           : run_tick_cd<R, false, LOCAL, PROT>(s, cols, c);
                 if (pr.target > 0 && track_max) {
                     // Under an external target, ticks below it are not replayed; keep the
                     // largest H seen in the running best (a valid lower bound of the optimum)
@@ -754,7 +855,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     for (int k = 0; k < R; ++k) want[k] = true;
                     RowBest<R> rb;
                     load_rb(rb);
-                    run_tick<R, LOCAL, kExact, false, CD>(s, rb, cols, c, want);
+                    run_tick<R, LOCAL, kExact, false, CD, PROT>(s, rb, cols, c, want);
                     store_rb(rb);
                     publish_best(rb, want);
                     refresh_sb(rb);
@@ -772,8 +873,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 // Shifted-domain builds take this path only for slow ticks (and, in
                 // principle, untracked problems): the predicated form serves both
                 // and keeps the fast plain loop out of those builds.
-                if (slow || CD) run_tick<R, LOCAL, kRun, true, CD>(s, rb, cols, c, want);
-                else run_tick<R, LOCAL, kRun, false, CD>(s, rb, cols, c, want);
+                if (slow || CD) run_tick<R, LOCAL, kRun, true, CD, PROT>(s, rb, cols, c, want);
+                else run_tick<R, LOCAL, kRun, false, CD, PROT>(s, rb, cols, c, want);
 
                 if (pr.track) {
                     bool any = false;
@@ -787,8 +888,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                     if (__any(any)) {
                         // Replay from the snapshot; the replay ends in the same state.
                         restore();
-                        if (slow || CD) run_tick<R, LOCAL, kTrack, true, CD>(s, rb, cols, c, want);
-                        else run_tick<R, LOCAL, kTrack, false, CD>(s, rb, cols, c, want);
+                        if (slow || CD) run_tick<R, LOCAL, kTrack, true, CD, PROT>(s, rb, cols, c, want);
+                        else run_tick<R, LOCAL, kTrack, false, CD, PROT>(s, rb, cols, c, want);
                         publish_best(rb, want);
                     }
                 }
@@ -858,26 +959,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 
 // ------------------------------------------------------------------------ small kernels
 
-__device__ __forceinline__ uint8_t encode_letter(uint8_t ch, bool& ok) {
+// DNA: A C G T (either case) -> 0..3.  Matrix scoring: the letter's class.
+// Anything else is rejected and written as the padding code.
+__device__ __forceinline__ uint8_t encode_letter(uint8_t ch, const EncTable& tab, bool& ok) {
+    if (!tab.dna) {
+        const int c = tab.cls[ch];
+        ok = c >= 0;
+        return ok ? (uint8_t)c : (uint8_t)tab.pad_code;
+    }
     ch &= 0xDF;  // upper case
     const uint8_t code = ch == 'A' ? 0 : ch == 'C' ? 1 : ch == 'G' ? 2 : ch == 'T' ? 3 : 0xff;
     ok = code != 0xff;
     return ok ? code : kPadCode;
 }
 
-// mode: bit 0 reverses the sequence, bit 1 complements it (A<->T, C<->G: code ^ 3).
+// mode: bit 0 reverses the sequence, bit 1 complements it (DNA: A<->T, C<->G: code ^ 3).
 __global__ void encode_kernel(const uint8_t* __restrict__ src, int64_t n, uint8_t* __restrict__ dst,
-                              int64_t pad_before, int64_t pad_after, int mode, unsigned long long* bad) {
+                              int64_t pad_before, int64_t pad_after, int mode, EncTable tab,
+                              unsigned long long* bad) {
     const int64_t total = pad_before + n + pad_after;
     const uint8_t flip = (mode & 2) ? 3 : 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = i - pad_before;
-        uint8_t code = kPadCode;
+        uint8_t code = (uint8_t)tab.pad_code;
         if (j >= 0 && j < n) {
             const int64_t sj = (mode & 1) ? n - 1 - j : j;
             bool ok;
-            code = encode_letter(src[sj], ok);
+            code = encode_letter(src[sj], tab, ok);
             if (!ok) atomicMax(bad, (1ull << 62) - (unsigned long long)sj);  // largest value = first offset
             else code ^= flip;
         }
@@ -889,12 +998,12 @@ __global__ void encode_kernel(const uint8_t* __restrict__ src, int64_t n, uint8_
 // Padding around the destinations is written by the caller (zero kernel + pad fill).
 __global__ void encode_many_kernel(const uint8_t* __restrict__ src, const int64_t* __restrict__ src_off,
                                    const int64_t* __restrict__ dst_off, const int64_t* __restrict__ len,
-                                   int64_t n, uint8_t* __restrict__ dst, unsigned long long* bad) {
+                                   int64_t n, uint8_t* __restrict__ dst, EncTable tab, unsigned long long* bad) {
     for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
         const int64_t so = src_off[k], d = dst_off[k], L = len[k];
         for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
             bool ok;
-            const uint8_t code = encode_letter(src[so + i], ok);
+            const uint8_t code = encode_letter(src[so + i], tab, ok);
             if (!ok) atomicMax(bad, (1ull << 62) - (unsigned long long)(so + i));
             dst[d + i] = code;
         }
@@ -981,19 +1090,22 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TaskRec* __restrict__
 // ------------------------------------------------------------------------ launchers
 
 hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
-                         int mode, unsigned long long* bad, hipStream_t st) {
+                         int mode, const EncTable& tab, unsigned long long* bad, hipStream_t st) {
+    if ((mode & ENC_COMPLEMENT) && !tab.dna) return hipErrorInvalidValue;
     const int64_t total = pad_before + n + pad_after;
     const int blocks = (int)min((int64_t)4096, (total + 255) / 256);
     hipLaunchKernelGGL(encode_kernel, dim3(max(blocks, 1)), dim3(256), 0, st, src, n, dst, pad_before, pad_after,
-                       mode, bad);
+                       mode, tab, bad);
     return hipGetLastError();
 }
 
 hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
-                              const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad, hipStream_t st) {
+                              const int64_t* len, int64_t n, uint8_t* dst, const EncTable& tab,
+                              unsigned long long* bad, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int blocks = (int)min((int64_t)8192, n);
-    hipLaunchKernelGGL(encode_many_kernel, dim3(blocks), dim3(256), 0, st, src, src_off, dst_off, len, n, dst, bad);
+    hipLaunchKernelGGL(encode_many_kernel, dim3(blocks), dim3(256), 0, st, src, src_off, dst_off, len, n, dst, tab,
+                       bad);
     return hipGetLastError();
 }
 
@@ -1011,16 +1123,26 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
 template <bool LOCAL, bool CD>
 static void launch_variant(const EngineArgs& args, int R, int occ, dim3 g, hipStream_t st) {
     const dim3 b(kWave);
-    if (R == 6 && occ <= 2) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 2>), g, b, 0, st, args);
-    else if (R == 6) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 3>), g, b, 0, st, args);
-    else if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4>), g, b, 0, st, args);
-    else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2>), g, b, 0, st, args);
-    else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3>), g, b, 0, st, args);
+    if (args.sub.n_class > 0) {  // matrix scoring: the query profile in dynamic LDS
+        const size_t lds = (size_t)args.sub.n_class * kWave * (R == 4 ? 4 : 8);
+        if (R == 6 && occ <= 2) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 2, true>), g, b, lds, st, args);
+        else if (R == 6) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 3, true>), g, b, lds, st, args);
+        else if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4, true>), g, b, lds, st, args);
+        else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2, true>), g, b, lds, st, args);
+        else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3, true>), g, b, lds, st, args);
+        return;
+    }
+    if (R == 6 && occ <= 2) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 2, false>), g, b, 0, st, args);
+    else if (R == 6) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 3, false>), g, b, 0, st, args);
+    else if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4, false>), g, b, 0, st, args);
+    else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2, false>), g, b, 0, st, args);
+    else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3, false>), g, b, 0, st, args);
 }
 
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st) {
     if (rows_per_lane != 4 && rows_per_lane != 6 && rows_per_lane != 8) return hipErrorInvalidValue;
+    if (args.sub.n_class < 0 || args.sub.n_class > kMaxClasses) return hipErrorInvalidValue;
     const int occ = (waves_per_cu + 3) / 4;  // waves per SIMD (4 SIMDs per CU)
     const dim3 g(grid);
     if (local && cd) launch_variant<true, true>(args, rows_per_lane, occ, g, st);

@@ -145,11 +145,12 @@ sw_status swmi::run_score_halves(sw_context* ctx, const uint8_t* d_a, int64_t M,
     MidResult* d_res = (MidResult*)(base + L.res);
     uint8_t* eng = base + L.eng;
     hipStream_t s = ctx->stream;
+    const EncTable et = enc_table(sc);
     HIP_TRY(launch_zero(flags, 256, s));
-    HIP_TRY(launch_encode(d_a, M, fa, 0, 64, 0, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_b, N, fb, kBPad, kBPadTail, 0, (unsigned long long*)(flags + 8), s));
-    HIP_TRY(launch_encode(d_a, M, rva, 0, 64, 1, (unsigned long long*)flags, s));
-    HIP_TRY(launch_encode(d_b, N, rvb, kBPad, kBPadTail, 1, (unsigned long long*)(flags + 8), s));
+    HIP_TRY(launch_encode(d_a, M, fa, 0, 64, 0, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_b, N, fb, kBPad, kBPadTail, 0, et, (unsigned long long*)(flags + 8), s));
+    HIP_TRY(launch_encode(d_a, M, rva, 0, 64, ENC_REVERSE, et, (unsigned long long*)flags, s));
+    HIP_TRY(launch_encode(d_b, N, rvb, kBPad, kBPadTail, ENC_REVERSE, et, (unsigned long long*)(flags + 8), s));
     HIP_TRY(launch_fill_i32(oh, kNeg, (size_t)(2 * (N + 1)), s));
     HIP_TRY(launch_fill_i32(of, kNeg, (size_t)(2 * (N + 1)), s));
 
@@ -170,8 +171,8 @@ sw_status swmi::run_score_halves(sw_context* ctx, const uint8_t* d_a, int64_t M,
     unsigned long long bad_a, bad_b;
     std::memcpy(&bad_a, hm, 8);
     std::memcpy(&bad_b, hm + 8, 8);
-    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_a);
-    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not one of ACGTacgt", kBadBase - bad_b);
+    if (bad_a) return fail(SW_EINVAL, "sequence a: byte at offset %llu is not %s", kBadBase - bad_a, letters_text(sc));
+    if (bad_b) return fail(SW_EINVAL, "sequence b: byte at offset %llu is not %s", kBadBase - bad_b, letters_text(sc));
     ScoreOut so[2];
     std::memcpy(so, hm + 64, sizeof so);
     MidResult mr;

@@ -363,8 +363,10 @@ sw_status features_one(sw_context* ctx, const uint8_t* d_a, int64_t na, const ui
     unsigned int* band = (unsigned int*)((uint8_t*)pos + align_up((size_t)na * 4 + 64, 256));
     unsigned long long* bad = (unsigned long long*)((uint8_t*)band + align_up((size_t)nbands * 4, 256));
     HIP_TRY(launch_zero(bad, 16, s));
-    HIP_TRY(launch_encode(d_a, na, ca, 0, 64, 0, bad, s));
-    HIP_TRY(launch_encode(d_b, nb, cb, 0, 64, 0, bad + 1, s));
+    const sw_scoring dna{1, 3, 5, 2, nullptr};  // the features are DNA k-mers
+    const EncTable et = enc_table(&dna);
+    HIP_TRY(launch_encode(d_a, na, ca, 0, 64, 0, et, bad, s));
+    HIP_TRY(launch_encode(d_b, nb, cb, 0, 64, 0, et, bad + 1, s));
     HIP_TRY(launch_zero(cnt_a, 2 * 512 + align_up(kBins * 4, 256), s));
     HIP_TRY(launch_zero(counts, (size_t)kK12 * 4, s));
     HIP_TRY(launch_zero(cursor, (size_t)kK12 * 4, s));

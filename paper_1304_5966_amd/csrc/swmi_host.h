@@ -86,7 +86,19 @@ size_t align_up(size_t v, size_t a);
 const char* engine_status_text(int32_t status);
 sw_status fail(sw_status st, const char* fmt, ...);
 sw_status ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out);
-sw_status check_scoring(const sw_scoring* s);
+// Checks a caller's scoring and writes the copy the library works with: with a
+// substitution matrix, match = max(1, largest entry) and mismatch = max(0,
+// -smallest entry), so that every bound written with match holds.
+sw_status check_scoring(const sw_scoring* s, sw_scoring* norm);
+// Combinations the matrix scoring does not run (a threshold model, both strands).
+sw_status check_matrix_options(const sw_scoring* norm, const sw_options* o);
+// Encode table and substitution table of a checked scoring (n_class 0 for DNA).
+EncTable enc_table(const sw_scoring* sc);
+void subst_table(const sw_scoring* sc, Subst& out);
+// s(x, y) of two codes (DNA codes or matrix classes); -128 for the padding code.
+int32_t subst_score(const sw_scoring* sc, uint8_t x, uint8_t y);
+// The accepted letters, for error messages.
+const char* letters_text(const sw_scoring* sc);
 sw_status check_lengths(int64_t la, int64_t lb, const sw_scoring* s);
 sw_status check_options(const sw_options* o);
 

@@ -17,6 +17,23 @@ constexpr uint32_t kPadTable = 0x80808080u;
 constexpr int32_t kNeg = -(1 << 30);  // minus infinity of the global recurrence
 constexpr int64_t kNoBand = (int64_t)1 << 62;
 
+// Substitution-matrix scoring (protein alignment).  Letters are encoded as their
+// index in the matrix alphabet; the class after the last letter is the padding
+// class, whose row and column score -128 like kPadCode's.
+constexpr int kMaxClasses = 32;  // letters + the padding class
+struct Subst {
+    int8_t s[kMaxClasses][kMaxClasses];  // s[class of the A letter][class of the B letter]
+    int32_t n_class;                     // letters + 1 (0: match / mismatch scoring over ACGT)
+    int32_t pad_;
+};
+
+// Letter -> code table of the encode kernels (by value in the kernel arguments).
+struct EncTable {
+    int8_t cls[256];   // class of each byte, -1: not a letter (unused when dna)
+    int32_t dna;       // 1: ACGTacgt -> 0..3, padding kPadCode, complement = code ^ 3
+    int32_t pad_code;  // code written around column sequences and for rejected letters
+};
+
 
 // Border of a problem's DP matrix (row 0 or column 0).
 enum BorderKind : int32_t {
@@ -112,6 +129,7 @@ struct EngineArgs {
     const int32_t* top_f;    // and F (deletion-ending), as out_h/out_f write them
     uint32_t jitter;         // schedule-perturbation seed (tests; 0 = off)
     int32_t* abort_flag;     // set when a wait timed out (cleared per launch)
+    Subst sub;               // matrix scoring (n_class > 0): codes are letter classes
 };
 
 struct ScoreOut {
@@ -140,17 +158,20 @@ struct MidResult {
 hipError_t launch_midline(const MidTask* tasks, int64_t n, const int32_t* oh, const int32_t* of, int32_t g,
                           MidResult* out, hipStream_t st);
 
-// mode: ENC_REVERSE and/or ENC_COMPLEMENT (0: the letters as they are).
+// mode: ENC_REVERSE and/or ENC_COMPLEMENT (0: the letters as they are; the
+// complement exists for DNA only).
 enum { ENC_REVERSE = 1, ENC_COMPLEMENT = 2 };
 hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pad_before, int64_t pad_after,
-                         int mode, unsigned long long* bad, hipStream_t st);
+                         int mode, const EncTable& tab, unsigned long long* bad, hipStream_t st);
 hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
-                              const int64_t* len, int64_t n, uint8_t* dst, unsigned long long* bad,
-                              hipStream_t st);
-// cd: run the fast ticks in the column-shifted domain (requires
-// match + gap_extend <= 127).
+                              const int64_t* len, int64_t n, uint8_t* dst, const EncTable& tab,
+                              unsigned long long* bad, hipStream_t st);
+// cd: run the fast ticks in the column-shifted domain (requires every
+// substitution score plus gap_extend within -127..127).
 // waves_per_cu picks the register budget: rows_per_lane 8 and 6 run 2 waves per
 // SIMD (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
+// Matrix scoring (args.sub.n_class > 0) runs the same shapes; its launches take
+// n_class * 64 * (4 or 8) bytes of dynamic LDS for the stripe's query profile.
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
                          hipStream_t st);
 // rows_per_lane: the launch's R (records of tasks outside a kept band are skipped).

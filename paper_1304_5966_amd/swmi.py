@@ -36,9 +36,39 @@ class SwError(RuntimeError):
         self.status = status
 
 
+class Matrix(ctypes.Structure):
+    _fields_ = [("alphabet", ctypes.c_char_p), ("scores", ctypes.c_void_p),
+                ("size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Scoring(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
-                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32),
+                ("matrix", ctypes.POINTER(Matrix))]
+
+
+class MatrixScoring:
+    """Substitution-matrix scoring (protein alignment): s(x, y) = scores[i][j] for
+    x = alphabet[i] in A and y = alphabet[j] in B (letters case-insensitive), gaps as
+    in the (match, mismatch, open, extend) form.  Pass it wherever a scoring tuple goes."""
+
+    def __init__(self, alphabet: bytes, scores, gap_open: int, gap_extend: int):
+        self.alphabet = bytes(alphabet)
+        self.scores = np.ascontiguousarray(scores, dtype=np.int8)
+        self.gap_open, self.gap_extend = int(gap_open), int(gap_extend)
+
+    def struct(self) -> Scoring:
+        m = Matrix(self.alphabet, self.scores.ctypes.data, len(self.alphabet), 0)
+        sc = Scoring(0, 0, self.gap_open, self.gap_extend, ctypes.pointer(m))
+        sc._keep = (m, self.scores)  # the matrix stays alive while the struct does
+        return sc
+
+
+def _scoring(scoring):
+    """ctypes reference to an sw_scoring for a (match, mismatch, open, extend) tuple or a
+    MatrixScoring; the object returned keeps everything it points to alive."""
+    sc = scoring.struct() if isinstance(scoring, MatrixScoring) else Scoring(*scoring)
+    return ctypes.byref(sc)
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64)
@@ -266,14 +296,14 @@ class Context:
     def score(self, a, b, scoring=DEFAULT_SCORING, **opts) -> Score:
         a, b = _bytes(a), _bytes(b)
         r = ScoreResult()
-        _check(lib.sw_score(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+        _check(lib.sw_score(self.handle, a, len(a), b, len(b), _scoring(scoring),
                             ctypes.byref(_options(**opts)), ctypes.byref(r)))
         return _score_of(r)
 
     def align(self, a, b, scoring=DEFAULT_SCORING, **opts) -> Alignment:
         a, b = _bytes(a), _bytes(b)
         r = AlignResult()
-        _check(lib.sw_align(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+        _check(lib.sw_align(self.handle, a, len(a), b, len(b), _scoring(scoring),
                             ctypes.byref(_options(**opts)), ctypes.byref(r)))
         try:
             cig = ctypes.string_at(r.cigar, r.cigar_len).decode() if r.cigar else ""
@@ -284,7 +314,7 @@ class Context:
     def start(self, a, b, score, end_a, end_b, scoring=DEFAULT_SCORING):
         a, b = _bytes(a), _bytes(b)
         sa, sb = ctypes.c_int64(), ctypes.c_int64()
-        _check(lib.sw_start(self.handle, a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)),
+        _check(lib.sw_start(self.handle, a, len(a), b, len(b), _scoring(scoring),
                             int(score), int(end_a), int(end_b), ctypes.byref(sa), ctypes.byref(sb)))
         return sa.value, sb.value
 
@@ -304,7 +334,7 @@ class Context:
         out = (ScoreResult * max(n, 1))()
         i64p = ctypes.POINTER(ctypes.c_int64)
         _check(lib.sw_batch(self.handle, _bytes(seqs_a), offs_a.ctypes.data_as(i64p), _bytes(seqs_b),
-                            offs_b.ctypes.data_as(i64p), n, ctypes.byref(Scoring(*scoring)),
+                            offs_b.ctypes.data_as(i64p), n, _scoring(scoring),
                             ctypes.byref(_options(**opts)), out))
         return BatchResults(out, n)
 
@@ -315,7 +345,8 @@ class Context:
         offs_b = np.ascontiguousarray(offs_b, dtype=np.int64)
         n = len(offs_a) - 1
         i64p = ctypes.POINTER(ctypes.c_int64)
-        sc, op = Scoring(*scoring), _options(**opts)
+        sc = scoring.struct() if isinstance(scoring, MatrixScoring) else Scoring(*scoring)
+        op = _options(**opts)
         if workspace is None:  # the library checks a caller's workspace itself
             workspace = self.workspace(int(lib.sw_batch_workspace_size(
                 self.handle, offs_a.ctypes.data_as(i64p), offs_b.ctypes.data_as(i64p), n, ctypes.byref(sc),
@@ -334,7 +365,7 @@ class Context:
         i64p = ctypes.POINTER(ctypes.c_int64)
         return int(lib.sw_batch_workspace_size(self.handle, offs_a.ctypes.data_as(i64p),
                                                offs_b.ctypes.data_as(i64p), len(offs_a) - 1,
-                                               ctypes.byref(Scoring(*scoring)),
+                                               _scoring(scoring),
                                                ctypes.byref(_options(**opts))))
 
     # -- device-pointer entry point (torch-owned buffers, no allocation in the library)
@@ -354,7 +385,7 @@ class Context:
         ws = workspace if workspace is not None else self.workspace(need)
         r = ScoreResult()
         _check(lib.sw_score_dev(self.handle, ctypes.c_void_p(d_a.data_ptr()), la,
-                                ctypes.c_void_p(d_b.data_ptr()), lb, ctypes.byref(Scoring(*scoring)),
+                                ctypes.c_void_p(d_b.data_ptr()), lb, _scoring(scoring),
                                 ctypes.byref(_options(**opts)), ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel(), ctypes.byref(r)))
         return _score_of(r)
@@ -365,7 +396,7 @@ class Context:
         r = ScoreResult()
         _check(lib.sw_score_dev_noalloc(self.handle, ctypes.c_void_p(d_a.data_ptr()), int(d_a.numel()),
                                         ctypes.c_void_p(d_b.data_ptr()), int(d_b.numel()),
-                                        ctypes.byref(Scoring(*scoring)), ctypes.byref(_options(**opts)),
+                                        _scoring(scoring), ctypes.byref(_options(**opts)),
                                         ctypes.byref(r)))
         return _score_of(r)
 
@@ -459,7 +490,7 @@ def mm_host(a, b, scoring=DEFAULT_SCORING, tb=-1, te=-1, score=None) -> str:
     cap = 4 * (len(a) + len(b)) + 64
     buf = ctypes.create_string_buffer(cap)
     n = ctypes.c_int64()
-    _check(lib.sw_mm_host(a, len(a), b, len(b), ctypes.byref(Scoring(*scoring)), tb, te,
+    _check(lib.sw_mm_host(a, len(a), b, len(b), _scoring(scoring), tb, te,
                           0 if score is None else 1, 0 if score is None else int(score), buf, cap,
                           ctypes.byref(n)))
     return buf.value.decode()

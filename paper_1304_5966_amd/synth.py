@@ -1,4 +1,4 @@
-"""Seeded synthetic DNA workloads.
+"""Seeded synthetic DNA (and protein) workloads.
 
 This module only *generates sequences*: iid bases, point substitutions,
 insertions and deletions, segment shuffles and reverse complements.  The edit
@@ -412,3 +412,85 @@ def homologous_pair(seed: int, la: int, lb: int, div: float = 0.1) -> Pair:
     rng = rng_for(seed, la, lb, 1)
     a = random_dna(rng, la)
     return embed_homolog(rng, a, lb, min(la, lb), 0.9 * div, 0.1 * div)
+
+
+# --------------------------------------------------------------------------- protein
+
+AMINO = b"ARNDCQEGHILKMFPSTWYV"  # the 20 amino-acid letters
+
+
+def substitution_matrix(seed: int, k: int = 20, symmetric: bool = True) -> np.ndarray:
+    """A seeded k x k int8 matrix in the value range of the usual protein matrices:
+    diagonal 4..11, off-diagonal -4..2 (the paper prints no matrix, so tests and the
+    benchmark draw one)."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(-4, 3, size=(k, k))
+    if symmetric:
+        m = np.triu(m) + np.triu(m, 1).T
+    np.fill_diagonal(m, rng.integers(4, 12, size=k))
+    return m.astype(np.int8)
+
+
+def mutate_letters(rng: np.random.Generator, src: np.ndarray, alphabet: bytes, sub_rate: float,
+                   indel_rate: float, mean_indel: float = 3.0) -> np.ndarray:
+    """Copy ``src`` (letters of ``alphabet``) with substitutions to a uniform other letter
+    and geometric-length insertions of random letters / deletions, as ``mutate`` does for DNA."""
+    al = np.frombuffer(alphabet, dtype=np.uint8)
+    k = al.size
+    lut = np.zeros(256, dtype=np.int64)
+    lut[al] = np.arange(k)
+    codes = lut[np.asarray(src, dtype=np.uint8)]
+    n = codes.size
+    sub = rng.random(n) < sub_rate
+    if k > 1 and sub.any():
+        codes = codes.copy()
+        codes[sub] = (codes[sub] + rng.integers(1, k, size=int(sub.sum()))) % k
+    pieces, pos = [], 0
+    for p in np.nonzero(rng.random(n) < indel_rate)[0].tolist():
+        if p < pos:
+            continue
+        L = int(rng.geometric(1.0 / mean_indel))
+        pieces.append(codes[pos:p])
+        if rng.random() < 0.5:
+            pieces.append(rng.integers(0, k, size=L))
+            pos = p
+        else:
+            pos = min(n, p + L)
+    pieces.append(codes[pos:])
+    return al[np.concatenate(pieces)] if pieces else np.zeros(0, dtype=np.uint8)
+
+
+def protein_pair(seed: int, la: int, lb: int, div: float = 0.3, alphabet: bytes = AMINO) -> Pair:
+    """A: iid letters of ``alphabet``; B: a mutated copy (divergence ``div``, 90 % substitutions,
+    10 % indel events) of min(la, lb) letters of A at a random offset, in random flanks,
+    trimmed or padded to lb."""
+    rng = rng_for(seed, la, lb, 7)
+    al = np.frombuffer(alphabet, dtype=np.uint8)
+    a = al[rng.integers(0, al.size, size=la)]
+    core_len = min(la, lb)
+    off = int(rng.integers(0, la - core_len + 1)) if la else 0
+    core = mutate_letters(rng, a[off:off + core_len], alphabet, 0.9 * div, 0.1 * div)[:lb]
+    left = int(rng.integers(0, lb - core.size + 1))
+    b = np.concatenate((al[rng.integers(0, al.size, size=left)], core,
+                        al[rng.integers(0, al.size, size=lb - core.size - left)]))
+    return Pair(a, b.astype(np.uint8), [], True, "protein")
+
+
+SEED_PROTEIN = 13045973
+N_PROTEIN = 20_000
+
+
+def protein_batch_pair(i: int, seed: int = SEED_PROTEIN) -> Pair:
+    """Pair i of the protein batch: lengths log-uniform 100..10 000 letters per side; even
+    pairs homologous (divergence 10..60 %), odd pairs unrelated."""
+    rng = rng_for(seed, i)
+    la, lb = loguniform_len(rng, 100, 10_000), loguniform_len(rng, 100, 10_000)
+    if i % 2 == 0:
+        return protein_pair(int(rng.integers(1 << 62)), la, lb, float(rng.uniform(0.1, 0.6)))
+    al = np.frombuffer(AMINO, dtype=np.uint8)
+    return Pair(al[rng.integers(0, al.size, size=la)], al[rng.integers(0, al.size, size=lb)], [], False, "protein")
+
+
+def protein_batch(n: int = N_PROTEIN, seed: int = SEED_PROTEIN) -> list:
+    return [protein_batch_pair(i, seed) for i in range(n)]
+

@@ -131,25 +131,30 @@ def test_config2_alignment_properties(ctx, orc):
     _check_windows(a, b, al, orc, np.random.default_rng(2))
 
 
-def test_config5_genome_scale_alignment(ctx, orc):
+def test_config5_genome_scale_alignment(ctx, orc, capsys):
     """The whole 32 Mbp x 28 Mbp genome-scale pair (8.96e14 cells): the score pass runs as
     row slabs of at most 1e14 cells (one launch each, progress printed between them) with
     running-best pruning, then the start pass and the reconstruction of the best alignment.
     Checked by rescoring, by every planted forward-strand segment as a lower bound, and by
     oracle-optimal windows of the path."""
     from paper_1304_5966_amd import swmi
-    _case("config5: generating the pair")
+
+    def say(msg):  # the test runs for minutes: its progress goes past the output capture
+        with capsys.disabled():
+            print(msg, flush=True)
+
+    say("[case] config5: generating the pair")
     p = synth.config5()
     a, b = p.a.tobytes(), p.b.tobytes()
     t0 = time.perf_counter()
 
     def progress(done, total):
-        print(f"config5 score pass: {done}/{total} rows ({time.perf_counter() - t0:.1f} s)", flush=True)
+        say(f"config5 score pass: {done}/{total} rows ({time.perf_counter() - t0:.1f} s)")
 
-    _case("config5 alignment (score pass in row slabs, running-best pruning)")
+    say("[case] config5 alignment (score pass in row slabs, running-best pruning)")
     al = ctx.align(a, b, prune=swmi.PRUNE_BEST, progress=progress)
-    print(f"config5 alignment {al.score} {al.start_a} {al.start_b} {al.end_a} {al.end_b} "
-          f"({time.perf_counter() - t0:.2f} s)", flush=True)
+    say(f"config5 alignment {al.score} {al.start_a} {al.start_b} {al.end_a} {al.end_b} "
+        f"({time.perf_counter() - t0:.2f} s)")
     assert orc.rescore(a, b, al.start_a, al.start_b, al.cigar) == (al.score, al.end_a, al.end_b)
     fwd = [pl for pl in p.planted if pl.strand == 0]
     assert fwd

@@ -94,3 +94,24 @@ def test_stratified_subset_keeps_the_mix():
     assert len(idx) == len(set(idx)) == 200 and idx == sorted(idx)
     assert sum(synth.config4_meta(i)[2] for i in idx) == 80
     assert eval_learned.stratified_subset(200) == idx
+
+
+def test_protein_generators():
+    m = synth.substitution_matrix(3)
+    assert m.dtype == np.int8 and m.shape == (20, 20) and (m == m.T).all()
+    assert (np.diag(m) >= 4).all() and (np.diag(m) <= 11).all()
+    off = m[~np.eye(20, dtype=bool)]
+    assert off.min() >= -4 and off.max() <= 2
+    assert not (synth.substitution_matrix(3, symmetric=False) == synth.substitution_matrix(3, symmetric=False).T).all()
+    for la, lb in [(1, 1), (300, 250), (64, 2000), (5000, 80)]:
+        p = synth.protein_pair(9, la, lb, 0.3)
+        assert (p.a.size, p.b.size) == (la, lb)
+        assert set(p.a.tobytes()) <= set(synth.AMINO) and set(p.b.tobytes()) <= set(synth.AMINO)
+        q = synth.protein_pair(9, la, lb, 0.3)
+        assert (p.a == q.a).all() and (p.b == q.b).all()
+    # a low divergence copy shares long exact runs with A
+    p = synth.protein_pair(4, 2000, 2000, 0.02)
+    assert p.b[100:140].tobytes() in p.a.tobytes() or p.b[1000:1040].tobytes() in p.a.tobytes()
+    batch = [synth.protein_batch_pair(i) for i in range(40)]
+    assert all(100 <= x.a.size <= 10_000 and 100 <= x.b.size <= 10_000 for x in batch)
+    assert [x.homologous for x in batch[:4]] == [True, False, True, False]
