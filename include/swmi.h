@@ -194,6 +194,14 @@ const char* sw_version(void);
 sw_status sw_context_create(int device, void* hip_stream, sw_context** out);
 sw_status sw_context_destroy(sw_context* ctx);
 
+/* Caps the device memory the context's host-pointer calls (sw_score, sw_align,
+ * sw_start, sw_batch) hold for inputs and workspace: a call that would need
+ * more fails with SW_ENOMEM before any device work.  0 (the default) = no
+ * limit.  Lowering the limit below what is held releases the held buffers
+ * (after the context's stream is idle).  The _dev calls use the caller's
+ * workspace and are not counted. */
+sw_status sw_context_set_max_workspace(sw_context* ctx, size_t bytes);
+
 /* Engine shape per workload class, set by a tuner that timed the candidates
  * on the device.  Calls whose options leave rows_per_lane / waves_per_cu at 0
  * take the class's tuned value (8 / 8 when untuned).  The class of a launch
@@ -213,6 +221,14 @@ sw_status sw_context_set_tuning(sw_context* ctx, int32_t tune_class, int32_t row
                                 int32_t waves_per_cu);
 sw_status sw_context_get_tuning(const sw_context* ctx, int32_t tune_class, int32_t* rows_per_lane,
                                 int32_t* waves_per_cu);
+
+/* Column band width of the class's local passes (score pass, batches), set by
+ * the tuner; calls whose options leave band_width at 0 take it.  0 = automatic:
+ * the widest band whose stripe hand-off slots fit 32 GiB.  A positive multiple
+ * of 64, else SW_EINVAL.  The banded global passes (start, reconstruction) size
+ * their bands from the alignment and ignore it. */
+sw_status sw_context_set_band_width(sw_context* ctx, int32_t tune_class, int32_t band_width);
+sw_status sw_context_get_band_width(const sw_context* ctx, int32_t tune_class, int32_t* band_width);
 
 /* First phase (paper Section 2): best local score and its endpoint.
  * a[0..len_a), b[0..len_b): host letters.  out: caller-owned. */

@@ -1,7 +1,7 @@
 """Tile-shape autotuner for the wavefront engine.
 
 The engine's shape has two knobs: rows per lane R (a stripe is 64*R rows) and
-resident stripe waves per CU.  More waves hide latency but lengthen the
+resident stripe waves per CU; long pairs add a third, the column band width.  More waves hide latency but lengthen the
 stripe pipeline's fill; larger R cuts the per-cell lane-exchange cost but
 needs more registers.  The best pair depends on the workload, so the tuner
 times each candidate on the caller's own data (through the C ABI; every
@@ -76,12 +76,32 @@ def _key(ctx, cls: int) -> str:
 
 def cached(ctx, cls: int):
     v = _load().get(_key(ctx, cls))
-    return None if v is None else {"rows_per_lane": v["rows_per_lane"], "waves_per_cu": v["waves_per_cu"]}
+    if v is None:
+        return None
+    out = {"rows_per_lane": v["rows_per_lane"], "waves_per_cu": v["waves_per_cu"]}
+    if "band_width" in v:
+        out["band_width"] = v["band_width"]
+    return out
 
 
 def _install(ctx, cls: int, best: dict) -> dict:
     ctx.set_tuning(cls, best["rows_per_lane"], best["waves_per_cu"])
+    if "band_width" in best:
+        ctx.set_band_width(cls, best["band_width"])
     return best
+
+
+def band_candidates(n_cols: int, grid: int, max_slot_bytes: float = 96 * 2**30) -> list:
+    """Column band widths to try for a pair of n_cols columns: the automatic width (0) and
+    the widths that cut the columns into 1, 3 and 4 equal bands, while the hand-off slots
+    (about one row of 8-byte entries per resident wave) stay within max_slot_bytes."""
+    out = [0]
+    for k in (1, 3, 4):
+        w = -(-n_cols // k)
+        w = -(-w // 64) * 64
+        if (grid + 1) * (w + 192) * 8 <= max_slot_bytes and w not in out:
+            out.append(w)
+    return out
 
 
 def _time(fn, reps, warm=True):
@@ -99,8 +119,9 @@ def _time(fn, reps, warm=True):
 
 
 def tune_score(ctx, d_a, d_b, crop: int | None = None, reps: int = 1, use_cache: bool = True, log=None,
-               table=None, candidates=None) -> dict:
-    """Best shape for one pair, timed on the pair (or its leading crop x crop).
+               table=None, candidates=None, tune_bands: bool = True) -> dict:
+    """Best shape for one pair, timed on the pair (or its leading crop x crop); for pairs of
+    10^10 cells and more, then the best column band width at that shape.
 
     ``table``, if a list, receives one dict per candidate (shape, seconds, GCUPS)."""
     la, lb = int(d_a.numel()), int(d_b.numel())
@@ -120,6 +141,23 @@ def tune_score(ctx, d_a, d_b, crop: int | None = None, reps: int = 1, use_cache:
             log(f"autotune {CLASS_NAMES[cls]} R={R} waves/CU={w}: {a.numel() * b.numel() / t / 1e9:.1f} GCUPS")
     t, R, w = min(rows)
     best = {"rows_per_lane": R, "waves_per_cu": w}
+    if tune_bands and cls in (swmi.TUNE_PAIR_LARGE, swmi.TUNE_PAIR_HUGE):
+        # then the column band width at that shape (wide bands keep the stripe pipeline full;
+        # fewer, narrower bands take less slot memory)
+        grid = swmi.torch.cuda.get_device_properties(ctx.device).multi_processor_count * w
+        bands = []
+        for bw in band_candidates(b.numel(), grid):
+            opts = dict(rows_per_lane=R, waves_per_cu=w, band_width=bw)
+            tb = t if bw == 0 else _time(lambda: ctx.score_dev(a, b, workspace=ctx.workspace(
+                ctx.workspace_size(a.numel(), b.numel(), **opts)), **opts), reps, warm=a.numel() * b.numel() < 1e11)
+            bands.append((tb, bw))
+            if table is not None:
+                table.append(dict(opts, s=round(tb, 4), gcups=round(a.numel() * b.numel() / tb / 1e9, 1)))
+            if log:
+                log(f"autotune {CLASS_NAMES[cls]} R={R} waves/CU={w} band {bw or 'auto'}: "
+                    f"{a.numel() * b.numel() / tb / 1e9:.1f} GCUPS")
+        t, bw = min(bands)
+        best["band_width"] = bw
     _store(_key(ctx, cls), dict(best, gcups=a.numel() * b.numel() / t / 1e9,
                                  sample=f"{a.numel()}x{b.numel()}"))
     return _install(ctx, cls, best)

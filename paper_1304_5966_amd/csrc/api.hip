@@ -131,6 +131,40 @@ extern "C" sw_status sw_context_set_tuning(sw_context* ctx, int32_t cls, int32_t
     return SW_OK;
 }
 
+extern "C" sw_status sw_context_set_max_workspace(sw_context* ctx, size_t bytes) {
+    if (!ctx) return fail(SW_EINVAL, "null context");
+    ctx->max_workspace_bytes = bytes;
+    size_t held = 0;
+    for (const auto& b : ctx->bufs) held += b.bytes;
+    if (bytes && held > bytes) {  // release what the new limit no longer covers
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        else (void)hipDeviceSynchronize();
+        for (auto& b : ctx->bufs) {
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+    }
+    return SW_OK;
+}
+
+extern "C" sw_status sw_context_set_band_width(sw_context* ctx, int32_t cls, int32_t band_width) {
+    if (!ctx) return fail(SW_EINVAL, "null context");
+    if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
+    if (band_width < 0 || band_width % kTick)
+        return fail(SW_EINVAL, "band_width must be 0 or a positive multiple of 64 (got %d)", band_width);
+    ctx->tuned_bw[cls] = band_width;
+    return SW_OK;
+}
+
+extern "C" sw_status sw_context_get_band_width(const sw_context* ctx, int32_t cls, int32_t* band_width) {
+    if (!ctx || !band_width) return fail(SW_EINVAL, "null argument");
+    if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
+    *band_width = ctx->tuned_bw[cls];
+    return SW_OK;
+}
+
 extern "C" sw_status sw_context_get_tuning(const sw_context* ctx, int32_t cls, int32_t* R, int32_t* wpc) {
     if (!ctx || !R || !wpc) return fail(SW_EINVAL, "null argument");
     if (cls < SW_TUNE_PAIR_SMALL || cls > SW_TUNE_BATCH) return fail(SW_EINVAL, "unknown tune class %d", cls);
@@ -141,6 +175,14 @@ extern "C" sw_status sw_context_get_tuning(const sw_context* ctx, int32_t cls, i
 
 sw_status swmi::ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out) {
     DevBuf& b = ctx->bufs[slot];
+    if (b.bytes < bytes && ctx->max_workspace_bytes) {
+        size_t held = 0;
+        for (int i = 0; i < BUF_COUNT; ++i)
+            if (i != slot) held += ctx->bufs[i].bytes;
+        if (held + bytes > ctx->max_workspace_bytes)
+            return fail(SW_ENOMEM, "the call needs %zu more bytes of device workspace; the context holds %zu and "
+                        "its limit is %zu (sw_context_set_max_workspace)", bytes, held, ctx->max_workspace_bytes);
+    }
     if (b.bytes < bytes) {
         if (b.ptr) {
             (void)hipStreamSynchronize(ctx->stream);
@@ -148,7 +190,8 @@ sw_status swmi::ctx_buffer(sw_context* ctx, int slot, size_t bytes, void** out) 
             b.ptr = nullptr;
             b.bytes = 0;
         }
-        const size_t want = std::max(bytes, (size_t)1 << 20);
+        size_t want = std::max(bytes, (size_t)1 << 20);
+        if (ctx->max_workspace_bytes) want = bytes;  // under a limit, no rounding up
         hipError_t e = hipMalloc(&b.ptr, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -343,6 +386,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     int64_t Wg = (int64_t)(slot_budget / ((size_t)nslot_est * sizeof(int2))) - (kSlotPad + 2 * kTick);
     Wg = std::max<int64_t>(kTick, Wg / kTick * kTick);
     if (band_width) Wg = band_width;
+    else if (local && ctx->tuned_bw[cls]) Wg = ctx->tuned_bw[cls];  // a tuned width (local passes only)
 
     int64_t task = 0, lrow = 0, Wmax = kTick;
     p.probs.reserve(specs.size());
@@ -505,6 +549,15 @@ static uint32_t schedule_jitter() {
     return (v && *v) ? (uint32_t)std::strtoul(v, nullptr, 10) : 0u;
 }
 
+// Longest wait of a launch before it gives up (ticks of the device's 100 MHz
+// real-time counter): SWMI_WAIT_LIMIT_US microseconds, 120 s if unset.  A tiny
+// limit is a test mode that drives the abort path without a hang.
+static uint64_t wait_limit_ticks() {
+    const char* v = std::getenv("SWMI_WAIT_LIMIT_US");
+    const unsigned long long us = (v && *v) ? std::strtoull(v, nullptr, 10) : 120000000ull;
+    return (uint64_t)std::max(1ull, std::min(us, 3600000000ull)) * 100ull;
+}
+
 // Kernel launches only (capturable in a HIP graph: no copies, no memsets).
 sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, const uint8_t* a_codes,
                                       const uint8_t* b_codes, const sw_scoring* sc, void* ws, int32_t* out_h,
@@ -546,6 +599,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     a.top_f = top_f;
     a.jitter = schedule_jitter();
     a.abort_flag = (int32_t*)(base + plan.off_misc + MISC_ABORT);
+    a.wait_limit = wait_limit_ticks();
     subst_table(sc, a.sub);
     for (const Prob& pr : plan.probs)
         if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))

@@ -200,7 +200,8 @@ uint64_t inputs_key(const sw_context* ctx, const uint8_t* d_a, const uint8_t* d_
                        (uint64_t)(uintptr_t)o->model, (uint64_t)o->rows_per_lane, (uint64_t)o->waves_per_cu,
                        (uint64_t)o->band_width, (uint64_t)o->flags})
         key = mix(key, v);
-    for (int c = 0; c < 4; ++c) key = mix(mix(key, (uint64_t)ctx->tuned_R[c]), (uint64_t)ctx->tuned_wpc[c]);
+    for (int c = 0; c < 4; ++c)
+        key = mix(mix(mix(key, (uint64_t)ctx->tuned_R[c]), (uint64_t)ctx->tuned_wpc[c]), (uint64_t)ctx->tuned_bw[c]);
     if (sc->matrix) {  // the matrix content (a replay bakes its table into the launch)
         const sw_matrix* m = sc->matrix;
         key = mix(key, (uint64_t)m->size);

@@ -99,18 +99,19 @@ __device__ __forceinline__ void publish_count(int32_t* p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Bounded waits.  A wait that has not ended after kWaitLimit ticks of the 100 MHz
-// real-time counter raises the launch's abort flag; from then on every wait of the
-// launch ends at once, the kernel runs to completion on meaningless values and the
-// host reports an internal error instead of hanging.
-constexpr uint64_t kWaitLimit = 120ull * 100000000ull;  // 120 s
+// Bounded waits.  A wait that has not ended after `limit` ticks of the 100 MHz
+// real-time counter (EngineArgs::wait_limit, 120 s unless the host sets another)
+// raises the launch's abort flag; from then on every wait of the launch ends at
+// once, the kernel runs to completion on meaningless values (every address comes
+// from the ticket table, none from values) and the host reports an internal
+// error instead of hanging.
 
 // Called on every unsuccessful poll; true: give up waiting.
-__device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t& t0, uint32_t& polls) {
+__device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t limit, uint64_t& t0, uint32_t& polls) {
     if (polls++ == 0) t0 = __builtin_amdgcn_s_memrealtime();
-    if ((polls & 255) != 0) return false;
+    if ((polls & 15) != 0) return false;  // every 16th poll (each poll is a memory round trip)
     if (load_count(abort_flag)) return true;
-    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitLimit) {
+    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return true;
     }
@@ -119,13 +120,13 @@ __device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t& t0
 
 // Waits until *flag >= need; `seen` caches the last value read.
 __device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need, int32_t& seen,
-                                              int32_t* abort_flag) {
+                                              int32_t* abort_flag, uint64_t limit) {
     uint64_t t0 = 0;
     uint32_t polls = 0;
     while (seen < need) {
         seen = load_count(flag);
         if (seen < need) {
-            if (wait_abandoned(abort_flag, t0, polls)) {
+            if (wait_abandoned(abort_flag, limit, t0, polls)) {
                 seen = need;
                 break;
             }
@@ -531,15 +532,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         // reader at all.
         if (task >= p.nslot) {
             int32_t seen = 0;
-            wait_at_least(p.progress + task - p.nslot, kDone, seen, p.abort_flag);
+            wait_at_least(p.progress + task - p.nslot, kDone, seen, p.abort_flag, p.wait_limit);
             if (tkt.reuse_reader >= 0) {
                 seen = 0;
-                wait_at_least(p.progress + tkt.reuse_reader, kDone, seen, p.abort_flag);
+                wait_at_least(p.progress + tkt.reuse_reader, kDone, seen, p.abort_flag, p.wait_limit);
             }
         }
         if (left_active) {
             int32_t seen = 0;
-            wait_at_least(p.progress + tkt.left, kDone, seen, p.abort_flag);
+            wait_at_least(p.progress + tkt.left, kDone, seen, p.abort_flag, p.wait_limit);
         }
 
         WaveState<R> s;
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 return make_int2(h, LOCAL ? 0 : kNeg);
             }
             if (!prod_active) return make_int2(kNeg, kNeg);
-            wait_at_least(prod_prog, need, prod_seen, p.abort_flag);
+            wait_at_least(prod_prog, need, prod_seen, p.abort_flag, p.wait_limit);
             return ld_shared_i2(prod_slot + kSlotPad + rel);
         };
         {
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 if (pr.top_kind == BORDER_BUF) h_diag = p.top_h[pr.top_off + c0];
                 else h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
             } else if (prod_active) {
-                wait_at_least(prod_prog, 1, prod_seen, p.abort_flag);
+                wait_at_least(prod_prog, 1, prod_seen, p.abort_flag, p.wait_limit);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
             } else if (band == 0) {
                 h_diag = border_h(pr.left_kind, pr.left_open, p.ext, R0);
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 // H(R0 - 1, c0 - 1): the last column of the previous band, captured by
                 // the task above-left (no task of that stripe after it writes the row)
                 int32_t seen = 0;
-                wait_at_least(p.progress + tkt.corner, kDone, seen, p.abort_flag);
+                wait_at_least(p.progress + tkt.corner, kDone, seen, p.abort_flag, p.wait_limit);
                 h_diag = ld_shared_i2(lbuf + R0 - 1).x;
             } else {
                 h_diag = kNeg;

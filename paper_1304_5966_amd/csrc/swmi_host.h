@@ -41,10 +41,12 @@ struct sw_context {
     // autotuned shapes per workload class (0 = not tuned): rows per lane, waves per CU
     int tuned_R[4] = {0, 0, 0, 0};
     int tuned_wpc[4] = {0, 0, 0, 0};
+    int tuned_bw[4] = {0, 0, 0, 0};      // column band width of local passes per class (0: automatic)
     void* scratch = nullptr;             // device address of the library's fixed scratch on `device`
     void* host_misc = nullptr;           // pinned 64 KiB for small host<->device copies
     size_t host_misc_bytes = 0;
     swmi::DevBuf bufs[swmi::BUF_COUNT];  // grow-only device buffers of the host-pointer API
+    size_t max_workspace_bytes = 0;      // cap on the sum of bufs (0: none; sw_context_set_max_workspace)
 };
 
 namespace swmi {

@@ -129,6 +129,7 @@ struct EngineArgs {
     const int32_t* top_f;    // and F (deletion-ending), as out_h/out_f write them
     uint32_t jitter;         // schedule-perturbation seed (tests; 0 = off)
     int32_t* abort_flag;     // set when a wait timed out (cleared per launch)
+    uint64_t wait_limit;     // a wait longer than this (ticks of the 100 MHz counter) aborts the launch
     Subst sub;               // matrix scoring (n_class > 0): codes are letter classes
 };
 

@@ -107,6 +107,9 @@ def _load():
     L.sw_context_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.sw_context_destroy.argtypes = [vp]
     L.sw_context_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.sw_context_set_max_workspace.argtypes = [vp, ctypes.c_size_t]
+    L.sw_context_set_band_width.argtypes = [vp, i32, i32]
+    L.sw_context_get_band_width.argtypes = [vp, i32, ctypes.POINTER(i32)]
     L.sw_context_get_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.sw_score.argtypes = [vp, ctypes.c_char_p, i64, ctypes.c_char_p, i64, ctypes.POINTER(Scoring),
                            ctypes.POINTER(Options), ctypes.POINTER(ScoreResult)]
@@ -284,8 +287,20 @@ class Context:
         except Exception:
             pass
 
+    def set_max_workspace(self, nbytes: int):
+        """Cap on the device memory of the host-pointer calls (0: none)."""
+        _check(lib.sw_context_set_max_workspace(self.handle, int(nbytes)))
+
     def set_tuning(self, tune_class: int, rows_per_lane: int, waves_per_cu: int):
         _check(lib.sw_context_set_tuning(self.handle, int(tune_class), int(rows_per_lane), int(waves_per_cu)))
+
+    def set_band_width(self, tune_class: int, band_width: int):
+        _check(lib.sw_context_set_band_width(self.handle, int(tune_class), int(band_width)))
+
+    def get_band_width(self, tune_class: int) -> int:
+        w = ctypes.c_int32()
+        _check(lib.sw_context_get_band_width(self.handle, int(tune_class), ctypes.byref(w)))
+        return w.value
 
     def get_tuning(self, tune_class: int):
         R, w = ctypes.c_int32(), ctypes.c_int32()

@@ -33,3 +33,16 @@ def test_cache_round_trip_and_corrupt_file(tmp_path, monkeypatch):
                     "gfx950:256:pair-huge": {"rows_per_lane": 8, "waves_per_cu": 8}}
     path.write_text("{not json")
     assert autotune._load() == {}
+
+
+def test_band_candidates():
+    from paper_1304_5966_amd import autotune
+    c = autotune.band_candidates(4_000_000, 2048)
+    assert c[0] == 0 and all(w % 64 == 0 for w in c[1:])
+    assert 4_000_000 <= c[1] < 4_000_064  # one band
+    assert c[2] * 3 >= 4_000_000 and c[3] * 4 >= 4_000_000
+    # widths whose slots would exceed the memory cap are left out
+    assert autotune.band_candidates(28_000_000, 2048) == [0]  # 7 Mi columns x 2049 slots > 96 GiB
+    assert autotune.band_candidates(28_000_000, 512) == [0, 9_333_376, 7_000_000]
+    assert autotune.band_candidates(100, 2048) == [0, 128, 64]
+

@@ -155,6 +155,20 @@ def test_tuning_is_used(ctx, orc):
         ctx.set_tuning(swmi.TUNE_BATCH, 16, 4)
     with pytest.raises(swmi.SwError):
         ctx.set_tuning(7, 8, 4)
+    # a tuned column band width (local passes), narrow enough to cut the pairs into many bands
+    for bw in (128, 1024, 0):
+        ctx.set_band_width(swmi.TUNE_BATCH, bw)
+        assert ctx.get_band_width(swmi.TUNE_BATCH) == bw
+        _case(f"tuned batch band width {bw}")
+        assert [g.key() for g in ctx.batch(pairs)] == exp
+    p = synth.homologous_pair(5, 3000, 2900, 0.1)
+    ctx.set_band_width(swmi.TUNE_PAIR_SMALL, 192)
+    assert ctx.score(p.a.tobytes(), p.b.tobytes()).key() == orc.sw_score(p.a.tobytes(), p.b.tobytes())
+    assert ctx.align(p.a.tobytes(), p.b.tobytes()).cigar == orc.sw_align(p.a.tobytes(), p.b.tobytes()).cigar
+    ctx.set_band_width(swmi.TUNE_PAIR_SMALL, 0)
+    for bad in (100, -64):
+        with pytest.raises(swmi.SwError):
+            ctx.set_band_width(swmi.TUNE_BATCH, bad)
 
 
 def test_batch_slot_reuse_across_problems(ctx, orc, monkeypatch):

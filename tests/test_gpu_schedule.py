@@ -81,3 +81,31 @@ def test_alignment_under_jitter(ctx, orc, jitter):
     al = ctx.align(a, b, rows_per_lane=4)
     assert (al.score, al.start_a, al.start_b, al.end_a, al.end_b, al.cigar) == \
         (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
+
+
+def test_wait_limit_abort_path(ctx, orc, monkeypatch):
+    """The bounded-wait failure path, forced from the host: with a wait limit of one
+    microsecond (and perturbed schedules, so that consumers wait), a wave gives up, raises the
+    launch's abort flag, every wait ends, the kernel completes and the call reports an internal
+    error instead of hanging.  Without the limit the same context gives exact results again."""
+    from paper_1304_5966_amd import swmi
+    p = synth.homologous_pair(31, 5000, 4800, 0.1)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    exp = orc.sw_score(a, b)
+    aborted = 0
+    for seed in (5, 6, 7):
+        monkeypatch.setenv("SWMI_WAIT_LIMIT_US", "1")
+        monkeypatch.setenv("SWMI_SCHEDULE_JITTER", str(seed))
+        _case(f"wait limit 1 us, jitter seed {seed}")
+        try:
+            r = ctx.score(a, b)
+            assert r.key() == exp  # no wait reached the limit: the result is exact
+        except swmi.SwError as e:
+            assert e.status == swmi.SW_EINTERNAL and "timed out" in str(e), e
+            aborted += 1
+        monkeypatch.delenv("SWMI_WAIT_LIMIT_US")
+        monkeypatch.delenv("SWMI_SCHEDULE_JITTER")
+        _case("default wait limit after the abort")
+        assert ctx.score(a, b).key() == exp
+        assert ctx.align(a, b).score == exp[0]
+    assert aborted > 0

@@ -116,6 +116,36 @@ def test_empty_and_errors(ctx):
         ctx.score(b"ACGT", b"ACGT", band_width=100)
 
 
+def test_workspace_limit(orc):
+    """A context's device-memory cap: a call beyond it fails with SW_ENOMEM before any device
+    work, a raised cap lets it run, and results are unchanged."""
+    from paper_1304_5966_amd import swmi
+    p = synth.homologous_pair(77, 3000, 2800, 0.1)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    exp = orc.sw_score(a, b)
+    c = swmi.Context(0)
+    try:
+        _case("workspace limit 64 KiB")
+        c.set_max_workspace(64 << 10)
+        for call in (lambda: c.score(a, b), lambda: c.align(a, b), lambda: c.batch([(a, b)])):
+            with pytest.raises(swmi.SwError) as e:
+                call()
+            assert e.value.status == swmi.SW_ENOMEM and "limit" in str(e.value)
+        _case("workspace limit raised")
+        c.set_max_workspace(1 << 30)
+        assert c.score(a, b).key() == exp
+        assert c.align(a, b).score == exp[0]
+        _case("workspace limit lowered below what is held")
+        c.set_max_workspace(64 << 10)
+        with pytest.raises(swmi.SwError) as e:
+            c.score(a, b)
+        assert e.value.status == swmi.SW_ENOMEM
+        c.set_max_workspace(0)
+        assert c.score(a, b).key() == exp
+    finally:
+        c.close()
+
+
 def test_other_scorings(ctx, orc):
     """Includes scorings at and beyond match + gap_extend = 127, where the local pass leaves the
     column-shifted domain for the plain one."""
