@@ -609,10 +609,10 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
     return SW_OK;
 }
 
-// Score of a CIGAR placed at (0, 0) of A' x B' (codes), or a consistency failure.
+// Score of a CIGAR placed at (0, 0) of A' x B' (codes: DNA 0..3 or matrix classes), or a
+// consistency failure.
 static bool rescore(const Cigar& c, const std::vector<uint8_t>& A, const std::vector<uint8_t>& B,
                     const sw_scoring* sc, int64_t& score, int64_t& ea, int64_t& eb) {
-    const EncTable et = enc_table(sc);
     int64_t i = 0, j = 0, s = 0;
     for (size_t k = 0; k < c.op.size(); ++k) {
         const char o = c.op[k];
@@ -620,11 +620,10 @@ static bool rescore(const Cigar& c, const std::vector<uint8_t>& A, const std::ve
         if (o == '=' || o == 'X') {
             for (int64_t t = 0; t < n; ++t, ++i, ++j) {
                 if (i >= (int64_t)A.size() || j >= (int64_t)B.size()) return false;
-                const uint8_t x = A[(size_t)i], y = B[(size_t)j];  // upper-case letters
+                const uint8_t x = A[(size_t)i], y = B[(size_t)j];  // codes: equal iff the letters are
                 const bool eq = x == y;
                 if (eq != (o == '=')) return false;
-                if (et.dna) s += eq ? sc->match : -sc->mismatch;
-                else s += subst_score(sc, (uint8_t)et.cls[x], (uint8_t)et.cls[y]);
+                s += subst_score(sc, x, y);
             }
         } else {
             s -= sc->gap_open + (int64_t)sc->gap_extend * (n - 1);
@@ -684,9 +683,16 @@ extern "C" sw_status sw_align(sw_context* ctx, const char* a, int64_t len_a, con
     if ((st = reconstruct(ctx, d_a + sa, d_b + sb, M, N, &nsc, sr.score, options, cig)) != SW_OK) return st;
     // consistency: the alignment must rescore to the best score and span the rectangle
     {
+        // codes of the letters (checked by the score pass): DNA 0..3, or matrix classes
+        const EncTable et = enc_table(&nsc);
+        auto code_of = [&](char ch) -> uint8_t {
+            if (!et.dna) return (uint8_t)et.cls[(uint8_t)ch];
+            const uint8_t u = (uint8_t)(ch & 0xDF);
+            return u == 'A' ? 0 : u == 'C' ? 1 : u == 'G' ? 2 : 3;
+        };
         std::vector<uint8_t> A((size_t)M), B((size_t)N);
-        for (int64_t i = 0; i < M; ++i) A[(size_t)i] = (uint8_t)(a[sa + i] & 0xDF);
-        for (int64_t j = 0; j < N; ++j) B[(size_t)j] = (uint8_t)(b[sb + j] & 0xDF);
+        for (int64_t i = 0; i < M; ++i) A[(size_t)i] = code_of(a[sa + i]);
+        for (int64_t j = 0; j < N; ++j) B[(size_t)j] = code_of(b[sb + j]);
         int64_t s2, ea, eb;
         if (!rescore(cig, A, B, &nsc, s2, ea, eb) || s2 != sr.score || ea != M - 1 || eb != N - 1)
             return fail(SW_EINTERNAL, "reconstruction does not rescore to the best score");

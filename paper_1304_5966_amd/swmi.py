@@ -55,6 +55,9 @@ class MatrixScoring:
     def __init__(self, alphabet: bytes, scores, gap_open: int, gap_extend: int):
         self.alphabet = bytes(alphabet)
         self.scores = np.ascontiguousarray(scores, dtype=np.int8)
+        k = len(self.alphabet)
+        if self.scores.shape != (k, k):  # the library reads size x size bytes
+            raise ValueError(f"scores must be {k} x {k} for a {k}-letter alphabet, got {self.scores.shape}")
         self.gap_open, self.gap_extend = int(gap_open), int(gap_extend)
 
     def struct(self) -> Scoring:

@@ -76,6 +76,10 @@ def test_protein_alphabets_and_gaps(ctx, orc, alphabet, symmetric, gaps):
         exp = orc.sw_score(a, b, o_sc)
         assert ctx.score(a, b, g_sc).key() == exp
         assert ctx.score(a, b, g_sc, prune=1, band_width=128).key() == exp
+        if la * lb < 2e6:  # the whole alignment, letters outside A-Z included ('*', digits)
+            e, g = orc.sw_align(a, b, o_sc), ctx.align(a, b, g_sc)
+            assert (g.score, g.start_a, g.start_b, g.end_a, g.end_b, g.cigar) == \
+                (e.score, e.start_a, e.start_b, e.end_a, e.end_b, e.cigar)
 
 
 @pytest.mark.parametrize("rows_per_lane", [4, 8])
