@@ -481,7 +481,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     __shared__ uint32_t b_ring[CD ? 2 : 1][kBring];
     // Row maxima and the pre-tick snapshot live in LDS (one column per lane) so
     // that the hot loop's registers hold only the recurrence.
-    __shared__ int lds_best[R][kWave], lds_pos[R][kWave];
+    // Matrix scoring at 2 waves per SIMD keeps them in registers instead (16 of the
+    // 256 VGPRs at R = 8): the LDS that frees lets the query profile fit 8 waves per CU.
+    constexpr bool kRbRegs = PROT && OCC <= 2;
+    __shared__ int lds_best[kRbRegs ? 1 : R][kWave], lds_pos[kRbRegs ? 1 : R][kWave];
     __shared__ int lds_snap[2 * R + 3][kWave];
     __shared__ __attribute__((aligned(16))) int2 out_buf[kTick];
     // Query profile (matrix scoring): entry (class c, lane l) at dword (c * 64 + l) * kPW
@@ -544,6 +547,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         }
 
         WaveState<R> s;
+        RowBest<R> rb_regs;  // kRbRegs: the row maxima between ticks
         const int M_rows = (int)max((int64_t)0, min((int64_t)R, pr.M - row0));
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -567,8 +571,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             s.H[k] = h;
             s.E[k] = e;
             s.HA[k] = h - p.open;
-            lds_best[k][lane] = LOCAL ? 0 : kNeg;
-            lds_pos[k][lane] = -1;
+            if constexpr (kRbRegs) {
+                rb_regs.best[k] = LOCAL ? 0 : kNeg;
+                rb_regs.pos[k] = -1;
+            } else {
+                lds_best[k][lane] = LOCAL ? 0 : kNeg;
+                lds_pos[k][lane] = -1;
+            }
         }
         if (PROT) {
             // This task's query profile.  Each lane writes and later reads only its
@@ -756,17 +765,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             }
 
             auto load_rb = [&](RowBest<R>& rb) {
+                if constexpr (kRbRegs) {
+                    rb = rb_regs;
+                } else {
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    rb.best[k] = lds_best[k][lane];
-                    rb.pos[k] = lds_pos[k][lane];
+                    for (int k = 0; k < R; ++k) {
+                        rb.best[k] = lds_best[k][lane];
+                        rb.pos[k] = lds_pos[k][lane];
+                    }
                 }
             };
             auto store_rb = [&](const RowBest<R>& rb) {
+                if constexpr (kRbRegs) {
+                    rb_regs = rb;
+                } else {
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    lds_best[k][lane] = rb.best[k];
-                    lds_pos[k][lane] = rb.pos[k];
+                    for (int k = 0; k < R; ++k) {
+                        lds_best[k][lane] = rb.best[k];
+                        lds_pos[k][lane] = rb.pos[k];
+                    }
                 }
             };
             auto snapshot = [&]() {
@@ -931,11 +948,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             int bv = kNeg, bk = 0, bp = -1;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const int b = lds_best[k][lane];
-                if (k < M_rows && b > bv) {
-                    bv = b;
-                    bk = k;
-                    bp = lds_pos[k][lane];
+                if constexpr (kRbRegs) {
+                    const int b = rb_regs.best[k];
+                    if (k < M_rows && b > bv) {
+                        bv = b;
+                        bk = k;
+                        bp = rb_regs.pos[k];
+                    }
+                } else {
+                    const int b = lds_best[k][lane];
+                    if (k < M_rows && b > bv) {
+                        bv = b;
+                        bk = k;
+                        bp = lds_pos[k][lane];
+                    }
                 }
             }
             const int vmax = wave_max(bv);
