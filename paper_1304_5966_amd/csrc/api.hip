@@ -486,25 +486,20 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
             live.resize(keep);
         }
     }
-    // Links, problem by problem (tick_of read in order).
-    std::vector<int32_t> reader((size_t)p.n_tickets, -1);  // ticket -> ticket of its slot's reader
-    for (int64_t pi = 0; pi < p.n_probs; ++pi) {
-        const Prob& pr = p.probs[pi];
+    // Links, in ticket order (the tickets are written sequentially; the problems and
+    // tick_of are read near the round-robin position).  The reader of a ticket's slot
+    // is its consumer, the stripe below.
+    for (int64_t j = 0; j < p.n_tickets; ++j) {
+        Ticket& tk = p.tickets[(size_t)j];
+        const Prob& pr = p.probs[tk.pi];
         const int32_t* tof = tick_of.data() + pr.task0;
-        for (int64_t l = 0; l < ntask[(size_t)pi]; ++l) {
-            const int32_t j = tof[l];
-            if (j < 0) continue;
-            Ticket& tk = p.tickets[(size_t)j];
-            const int64_t band = l / pr.Q, q = l - band * pr.Q;
-            tk.prod = q > 0 ? tof[l - 1] : -1;
-            tk.left = band > 0 ? tof[l - pr.Q] : -1;
-            tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tof[l - pr.Q - 1] : -1;
-            tk.cons = q + 1 < pr.Q ? tof[l + 1] : -1;
-            if (q + 1 < pr.Q) reader[(size_t)j] = tof[l + 1];
-        }
+        const int64_t l = tk.local, band = l / pr.Q, q = l - band * pr.Q;
+        tk.prod = q > 0 ? tof[l - 1] : -1;
+        tk.left = band > 0 ? tof[l - pr.Q] : -1;
+        tk.corner = (q > 0 && band > 0 && tk.prod < 0) ? tof[l - pr.Q - 1] : -1;
+        tk.cons = q + 1 < pr.Q ? tof[l + 1] : -1;
+        tk.reuse_reader = j >= p.nslot ? p.tickets[(size_t)(j - p.nslot)].cons : -1;
     }
-    for (int64_t j = 0; j < p.n_tickets; ++j)
-        p.tickets[(size_t)j].reuse_reader = j >= p.nslot ? reader[(size_t)(j - p.nslot)] : -1;
 
     size_t off = 0;
     p.off_tickets = off;

@@ -210,3 +210,30 @@ def test_batch_per_pair_thresholds(ctx, orc):
     for k, r in enumerate(res):
         assert r.threshold == T[k]
         assert r.fallback == (1 if T[k] > exp[k][0] else 0), k
+
+
+def test_autotuner_installs_shape_and_band_width(orc, tmp_path, monkeypatch):
+    """The tuner on a pair of 1e10 cells (the LARGE class): it times shapes, then column band
+    widths at the chosen shape, installs both in the context, and later calls that leave the
+    shape at 0 run with them; results equal the oracle's."""
+    import torch
+    from paper_1304_5966_amd import autotune, swmi
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    p = synth.homologous_pair(123, 100_000, 100_000, 0.1)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    exp = orc.sw_score_mt(a, b, threads=orc.host_cores())
+    c = swmi.Context(0)
+    try:
+        d_a, d_b = torch.from_numpy(p.a).cuda(), torch.from_numpy(p.b).cuda()
+        table = []
+        _case("autotune a 1e10-cell pair: shapes, then band widths")
+        best = autotune.tune_score(c, d_a, d_b, use_cache=False, table=table, candidates=[(8, 8), (4, 12)])
+        assert "band_width" in best
+        assert best["band_width"] in autotune.band_candidates(100_000, 256 * best["waves_per_cu"])
+        assert c.get_tuning(swmi.TUNE_PAIR_LARGE) == (best["rows_per_lane"], best["waves_per_cu"])
+        assert c.get_band_width(swmi.TUNE_PAIR_LARGE) == best["band_width"]
+        assert len(table) == 2 + len(autotune.band_candidates(100_000, 256 * best["waves_per_cu"]))
+        assert c.score_dev(d_a, d_b).key() == exp
+        assert autotune.cached(c, swmi.TUNE_PAIR_LARGE) == best
+    finally:
+        c.close()
