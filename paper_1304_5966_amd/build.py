@@ -28,7 +28,7 @@ def command(out: str):
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument",
             "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-            *sources(), "-o", out]
+            *sources(), "-L", "/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", out]
 
 
 def build(verbose: bool = False) -> str:

@@ -385,6 +385,7 @@ static int banded_rows(const sw_context* ctx, int64_t band_width_sum) {
 static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, const sw_scoring* sc,
                             int32_t score, int64_t end_a, int64_t end_b, const sw_options* o, int64_t* start_a,
                             int64_t* start_b) {
+    const Phase ph("swmi start pass");
     const int64_t M = end_a + 1, N = end_b + 1;
     ProbSpec ps;
     ps.a_off = 0;
@@ -468,6 +469,7 @@ static const int64_t kGpuRows = 2048;
 
 static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int64_t M, int64_t N,
                              const sw_scoring* sc, int64_t total_score, const sw_options* o, Cigar& cigar) {
+    const Phase ph("swmi reconstruction");
     const int64_t g = sc->gap_open - sc->gap_extend, h = sc->gap_extend;
     hipStream_t s = ctx->stream;
     // Codes: forward a | forward b (padded) | reversed a | reversed b (padded); plus host copies.
@@ -511,6 +513,7 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
         for (size_t i = 0; i < pieces.size(); ++i)
             if (pieces[i].is_sub && pieces[i].sub.M >= kGpuRows && pieces[i].sub.N > 0) big.push_back(i);
         if (big.empty()) break;
+        const Phase level("swmi reconstruction level");
         std::vector<ProbSpec> specs;
         std::vector<MidTask> mids;
         int64_t out_len = 0, maxband = 0, width_sum = 0;

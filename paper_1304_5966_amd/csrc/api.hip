@@ -721,6 +721,7 @@ static sw_status run_score_slabs(sw_context* ctx, const uint8_t* a_codes, int64_
     unsigned long long pruned[2] = {0, 0};
     int k = 0;
     for (int64_t r0 = 0; r0 < M; r0 += h, ++k) {
+        const Phase ph("swmi score slab");
         const int64_t r1 = std::min(M, r0 + h);
         std::vector<ProbSpec> specs = score_specs(r0, r1 - r0, N, o, S);
         for (int s = 0; s < S; ++s) {
@@ -774,6 +775,7 @@ static sw_status run_score_slabs(sw_context* ctx, const uint8_t* a_codes, int64_
 static sw_status run_score_once(sw_context* ctx, const uint8_t* d_a, int64_t M, const uint8_t* d_b, int64_t N,
                                 const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
                                 sw_score_result* out) {
+    const Phase ph("swmi score pass");
     const int S = strands_of(o);
     const int64_t h = slab_rows_for(M, N, o);
     const size_t rows_bytes = h ? 4 * slab_row_bytes(N, S) : 0;

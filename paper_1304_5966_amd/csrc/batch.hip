@@ -149,6 +149,7 @@ sw_status collect(const BatchLayout& L, const unsigned long long* flags, const S
 
 sw_status run_batch(sw_context* ctx, const uint8_t* d_a, const uint8_t* d_b, int32_t n, const sw_scoring* sc,
                     BatchLayout& L, void* ws, size_t ws_bytes, sw_score_result* out) {
+    const Phase ph("swmi batch launch");
     if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
     clear_out(out, n);
     if (L.specs.empty()) return SW_OK;

@@ -128,6 +128,7 @@ sw_status swmi::run_score_halves(sw_context* ctx, const uint8_t* d_a, int64_t M,
                                  const sw_scoring* sc, const sw_options* o, void* ws, size_t ws_bytes,
                                  sw_score_result* out) {
     if (M < 2) return fail(SW_EUNSUPPORTED, "two-halves score pass: needs at least two rows");
+    const Phase ph("swmi two-halves score pass");
     const HalvesLayout L = layout(ctx, M, N, o);
     if (ws_bytes < L.total) return fail(SW_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
     const int64_t mid = M / 2;

@@ -5,12 +5,24 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <vector>
 
 #include "swmi.h"
 #include "swmi_internal.h"
 
 namespace swmi {
+
+// A named range around a phase of the path (score pass, row slab, start pass,
+// reconstruction level, batch), for tracers that record roctx ranges (rocprofv3
+// --marker-trace); without a tracer the calls cost next to nothing.
+struct Phase {
+    explicit Phase(const char* name) { roctxRangePushA(name); }
+    ~Phase() { roctxRangePop(); }
+    Phase(const Phase&) = delete;
+    Phase& operator=(const Phase&) = delete;
+};
 
 struct DevBuf {
     void* ptr = nullptr;
