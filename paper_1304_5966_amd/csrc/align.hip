@@ -401,9 +401,7 @@ static sw_status start_pass(sw_context* ctx, const uint8_t* d_a, const uint8_t* 
     ps.d_lo = -G;
     ps.d_hi = G;
     const int R = o && o->rows_per_lane ? o->rows_per_lane : banded_rows(ctx, 2 * G + 1);
-    const int64_t bw = std::max<int64_t>(kTick, ((2 * G + kWave * R + 4 * kTick) / kTick) * kTick * 2);
-    const EnginePlan p = plan_engine(ctx, {ps}, false, R, o ? o->waves_per_cu : 0,
-                                     o && o->band_width ? o->band_width : (int)std::min<int64_t>(bw, 1 << 30));
+    const EnginePlan p = plan_engine(ctx, {ps}, false, R, o ? o->waves_per_cu : 0, o ? o->band_width : 0);
     const size_t cb = align_up((size_t)M + 64, 256) + align_up((size_t)(kBPad + N + kBPadTail), 256);
     void* ws;
     sw_status st = ctx_buffer(ctx, BUF_WORK, cb + 256 + p.total, &ws);
@@ -516,7 +514,7 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
         const Phase level("swmi reconstruction level");
         std::vector<ProbSpec> specs;
         std::vector<MidTask> mids;
-        int64_t out_len = 0, maxband = 0, width_sum = 0;
+        int64_t out_len = 0, width_sum = 0;
         for (size_t bi : big) {
             const Sub& sb = pieces[bi].sub;
             int64_t lo, hi;
@@ -559,12 +557,8 @@ static sw_status reconstruct(sw_context* ctx, const uint8_t* d_a, const uint8_t*
             specs.push_back(f);
             specs.push_back(r);
             mids.push_back(MidTask{f.out_off, r.out_off, sb.N});
-            if (lo > -kNoBand) maxband = std::max(maxband, hi - lo);
         }
-        const int64_t bw = maxband > 0 ? std::max<int64_t>(kTick, ((2 * maxband + kWave * R + 4 * kTick) / kTick) * kTick)
-                                       : 0;
-        const EnginePlan p = plan_engine(ctx, specs, false, R, o ? o->waves_per_cu : 0,
-                                         (int)std::min<int64_t>(bw, 1 << 30));
+        const EnginePlan p = plan_engine(ctx, specs, false, R, o ? o->waves_per_cu : 0, o ? o->band_width : 0);
         void* wbuf;
         const size_t out_bytes = align_up((size_t)out_len * sizeof(int32_t), 256);
         const size_t mid_bytes = align_up(mids.size() * sizeof(MidTask), 256);

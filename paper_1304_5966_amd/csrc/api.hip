@@ -337,6 +337,15 @@ sw_status swmi::check_options(const sw_options* o) {
 
 // ------------------------------------------------------------------------ engine plan
 
+// Waves per workgroup of the global passes' chain launches: SWMI_CHAIN_WAVES
+// (1 = off, 4 or 8), 4 if unset (on the 5 Mbp x 4 Mbp alignment: start pass 0.77 s
+// and reconstruction 0.52 s, against 0.83 / 1.03 s at 8 and 0.85 / 0.91 s at 1).
+static int chain_waves() {
+    const char* v = std::getenv("SWMI_CHAIN_WAVES");
+    const int w = (v && *v) ? std::atoi(v) : 4;
+    return (w == 4 || w == 8) ? w : 1;
+}
+
 // Slot memory a launch may take beyond its minimal ring: SWMI_SLOT_ROOM_BYTES
 // (bytes; 0 keeps the minimal ring), 8 GiB if unset.
 static size_t slot_room_bytes() {
@@ -385,10 +394,25 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     const size_t slot_budget = (size_t)32 << 30;
     int64_t Wg = (int64_t)(slot_budget / ((size_t)nslot_est * sizeof(int2))) - (kSlotPad + 2 * kTick);
     Wg = std::max<int64_t>(kTick, Wg / kTick * kTick);
+    // The global recurrence in a diagonal band: a stripe writes only the columns of
+    // the ticks that hold band cells, and its slot holds only those (slot_cols).
+    // Where such slots fit the budget, each problem is one column band: no stripe
+    // then waits for the stripe to its left to finish.
+    auto slot_cols = [&](const ProbSpec& s, int64_t W) -> int64_t {
+        const int64_t whole = W + 2 * kTick;
+        if (local || (s.d_lo <= -kNoBand && s.d_hi >= kNoBand)) return whole;
+        return std::min<int64_t>(whole, s.d_hi - s.d_lo + (int64_t)kWave * p.R + 4 * kTick);
+    };
+    if (!local && !band_width) {
+        int64_t cols = kTick;
+        for (const auto& s : specs) cols = std::max(cols, slot_cols(s, (s.N + kTick - 1) / kTick * kTick));
+        if ((size_t)nslot_est * (size_t)(kSlotPad + cols + 2 * kTick) * sizeof(int2) <= slot_budget)
+            Wg = (maxN + kTick - 1) / kTick * kTick;
+    }
     if (band_width) Wg = band_width;
     else if (local && ctx->tuned_bw[cls]) Wg = ctx->tuned_bw[cls];  // a tuned width (local passes only)
 
-    int64_t task = 0, lrow = 0, Wmax = kTick;
+    int64_t task = 0, lrow = 0, Wmax = kTick, Cmax = kTick;
     p.probs.reserve(specs.size());
     p.order.assign(order.begin(), order.end());
     for (size_t oi : order) {
@@ -419,6 +443,7 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
         task += pr.Q * pr.n_bands;
         if (pr.n_bands > 1) lrow += pr.Q * rows_per_stripe;
         Wmax = std::max(Wmax, pr.W);
+        Cmax = std::max(Cmax, slot_cols(s, pr.W));
         p.probs.push_back(pr);
     }
     p.n_probs = (int64_t)p.probs.size();
@@ -439,6 +464,10 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     }
     p.n_tickets = n_active;
     p.grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, n_active));
+    // The banded global passes at 4 rows per lane run in chain workgroups (consecutive
+    // stripes linked through LDS; with matrix scoring, or scores too large for the
+    // shifted domain, the launch runs one wave per workgroup on the same table).
+    p.chain = (!local && p.R == 4) ? chain_waves() : 1;
 
     // Ticket order.  Problems (largest first) go in groups of G; inside a group
     // the tasks go round-robin over the problems (task s of every problem that
@@ -451,9 +480,12 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     // slot per wave plus 2G, that reader is more than a whole generation of
     // waves older than k, so the wait is rare; and since nslot > G every ticket
     // waits only on older tickets.
+    // Chain launches take each problem's tasks in runs of `chain` (their waves link
+    // through LDS): a consumer is then at most G * chain tickets after its producer.
     const int64_t G = std::max<int64_t>(1, std::min<int64_t>(p.n_probs, (int64_t)p.grid));
-    p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1 + (G > 1 ? 2 * G : 0));
-    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + Wmax + 2 * kTick), 64);
+    const int64_t run = p.chain;
+    p.nslot = std::max<int64_t>(2, (int64_t)p.grid + 1 + (G > 1 ? 2 * G * run : 0));
+    p.slot_stride = (int64_t)align_up((size_t)(kSlotPad + (local ? Wmax + 2 * kTick : Cmax) + 2 * kTick), 64);
     // Where slots are small (many short problems), up to 8 GiB of them: tasks of
     // different sizes finish out of ticket order, and a slot whose last reader is
     // a long stripe would otherwise hold up the ticket that reuses it.
@@ -465,25 +497,49 @@ EnginePlan swmi::plan_engine(const sw_context* ctx, const std::vector<ProbSpec>&
     for (int64_t pi = 0; pi < p.n_probs; ++pi) ntask[(size_t)pi] = (int32_t)(p.probs[pi].Q * p.probs[pi].n_bands);
     int64_t k = 0;
     std::vector<int32_t> live;  // problems of the group with a task s, in table order
+    std::vector<int32_t> cursor;  // chain order: each live problem's next task
     for (int64_t g0 = 0; g0 < p.n_probs; g0 += G) {
         const int64_t g1 = std::min(p.n_probs, g0 + G);
         live.clear();
         for (int64_t pi = g0; pi < g1; ++pi)
             if (ntask[(size_t)pi] > 0) live.push_back((int32_t)pi);
-        for (int32_t s = 0; !live.empty(); ++s) {
-            size_t keep = 0;
-            for (const int32_t pi : live) {
-                const int64_t id = p.probs[pi].task0 + s;
-                if (!banded || active[(size_t)id]) {
-                    Ticket& tk = p.tickets[(size_t)k];
-                    tk.pi = pi;
-                    tk.local = s;
-                    tick_of[(size_t)id] = (int32_t)k;
-                    ++k;
+        if (run == 1) {
+            for (int32_t s = 0; !live.empty(); ++s) {
+                size_t keep = 0;
+                for (const int32_t pi : live) {
+                    const int64_t id = p.probs[pi].task0 + s;
+                    if (!banded || active[(size_t)id]) {
+                        Ticket& tk = p.tickets[(size_t)k];
+                        tk.pi = pi;
+                        tk.local = s;
+                        tick_of[(size_t)id] = (int32_t)k;
+                        ++k;
+                    }
+                    if (s + 1 < ntask[(size_t)pi]) live[keep++] = pi;
                 }
-                if (s + 1 < ntask[(size_t)pi]) live[keep++] = pi;
+                live.resize(keep);
             }
-            live.resize(keep);
+        } else {
+            // runs of `run` tickets (tasks with a cell in the band) per problem in turn
+            cursor.assign((size_t)(g1 - g0), 0);
+            while (!live.empty()) {
+                size_t keep = 0;
+                for (const int32_t pi : live) {
+                    int32_t& s = cursor[(size_t)(pi - g0)];
+                    for (int64_t taken = 0; taken < run && s < ntask[(size_t)pi]; ++s) {
+                        const int64_t id = p.probs[pi].task0 + s;
+                        if (banded && !active[(size_t)id]) continue;
+                        Ticket& tk = p.tickets[(size_t)k];
+                        tk.pi = pi;
+                        tk.local = s;
+                        tick_of[(size_t)id] = (int32_t)k;
+                        ++k;
+                        ++taken;
+                    }
+                    if (s < ntask[(size_t)pi]) live[keep++] = pi;
+                }
+                live.resize(keep);
+            }
         }
     }
     // Links, in ticket order (the tickets are written sequentially; the problems and
@@ -567,6 +623,23 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
             return fail(SW_EINTERNAL, "engine plan: ticket %lld waits on a younger ticket", (long long)k);
         if (t.cons >= plan.n_tickets || (t.cons >= 0 && t.cons <= k))
             return fail(SW_EINTERNAL, "engine plan: ticket %lld names consumer %d", (long long)k, t.cons);
+        if (!plan.local && t.cons >= 0) {
+            // the columns this task writes for its consumer fit its slot
+            const Prob& pr = plan.probs[(size_t)t.pi];
+            const int64_t band = t.local / pr.Q, q = t.local - band * pr.Q;
+            const int W = (int)std::min(pr.W, pr.N - band * pr.W);
+            const int n_ticks = (W + 2 * kTick - 2) / kTick;
+            int lo, hi, first, last;
+            band_ticks(pr, q * (int64_t)kWave * plan.R, band * pr.W, plan.R, n_ticks, lo, hi);
+            if (lo > hi) {
+                lo = 0;
+                hi = n_ticks - 1;
+            }
+            slot_columns(lo, hi, first, last);
+            if (last - first + 1 > plan.slot_stride - kSlotPad)
+                return fail(SW_EINTERNAL, "engine plan: ticket %lld writes %d columns to a slot of %lld", (long long)k,
+                            last - first + 1, (long long)(plan.slot_stride - kSlotPad));
+        }
     }
     EngineArgs a{};
     a.tickets = (const Ticket*)(base + plan.off_tickets);
@@ -600,7 +673,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
         if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))
             return fail(SW_EINTERNAL, "engine plan: a buffer top border without its row");
     const bool cd = sc->match + sc->gap_extend <= 127;
-    HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, st));
+    HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, plan.chain, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
                           a.pruned, a.abort_flag, st));
     return SW_OK;

@@ -106,16 +106,22 @@ __device__ __forceinline__ void publish_count(int32_t* p, int32_t v) {
 // from the ticket table, none from values) and the host reports an internal
 // error instead of hanging.
 
-// Called on every unsuccessful poll; true: give up waiting.
-__device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t limit, uint64_t& t0, uint32_t& polls) {
-    if (polls++ == 0) t0 = __builtin_amdgcn_s_memrealtime();
-    if ((polls & 15) != 0) return false;  // every 16th poll (each poll is a memory round trip)
+// True: give up waiting (the launch's abort flag is set, or this wait, begun at
+// t0, has run out; then it sets the flag).
+__device__ __forceinline__ bool wait_expired(int32_t* abort_flag, uint64_t limit, uint64_t t0) {
     if (load_count(abort_flag)) return true;
     if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return true;
     }
     return false;
+}
+
+// Called on every unsuccessful poll; true: give up waiting.
+__device__ __forceinline__ bool wait_abandoned(int32_t* abort_flag, uint64_t limit, uint64_t& t0, uint32_t& polls) {
+    if (polls++ == 0) t0 = __builtin_amdgcn_s_memrealtime();
+    if ((polls & 15) != 0) return false;  // every 16th poll (each poll is a memory round trip)
+    return wait_expired(abort_flag, limit, t0);
 }
 
 // Waits until *flag >= need; `seen` caches the last value read.
@@ -134,6 +140,57 @@ __device__ __forceinline__ void wait_at_least(const int32_t* flag, int32_t need,
         }
     }
     asm volatile("" ::: "memory");
+}
+
+// Chain workgroups (the banded global passes): K waves of one workgroup take K
+// consecutive tickets, which for a banded problem are consecutive stripes of one
+// band, and each hands its bottom row to the next wave through LDS instead of a
+// global slot.  LDS instructions of one wave are executed in order, so a value
+// written before a count is there for a wave that has read that count; the
+// accesses are relaxed atomics (no reordering by the compiler, no cache
+// maintenance).  The last wave of a group hands off through its global slot as
+// every other task does.
+constexpr int kRing = 4 * kTick;  // columns of a link ring (producer at most 4 ticks ahead)
+
+__device__ __forceinline__ int lds_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_store(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Waits until the LDS word *flag >= need.  An LDS poll is cheap, so the launch's
+// abort flag (a memory round trip) is read only every 256th poll.
+__device__ __forceinline__ void lds_wait_at_least(const int* flag, int need, int& seen, int32_t* abort_flag,
+                                                  uint64_t limit) {
+    uint64_t t0 = 0;
+    uint32_t polls = 0;
+    while (seen < need) {
+        seen = lds_load(flag);
+        if (seen < need) {
+            if (polls++ == 0) t0 = __builtin_amdgcn_s_memrealtime();
+            if ((polls & 255) == 0 && wait_expired(abort_flag, limit, t0)) {
+                seen = need;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    asm volatile("" ::: "memory");
+}
+
+// Orders the LDS accesses of one wave around a hand-off point (one wave per
+// workgroup: the workgroup barrier; chain workgroups: the wave alone).
+template <int K>
+__device__ __forceinline__ void wave_sync() {
+    if constexpr (K == 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // Schedule perturbation (a test mode; off when seed == 0): a wave-uniform
@@ -470,36 +527,72 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
 // (512 / OCC VGPRs per lane).
 // PROT: matrix scoring; the query profile takes p.sub.n_class * 64 * (4 or 8)
 // bytes of dynamic LDS.
-template <int R, bool LOCAL, bool CD, int OCC, bool PROT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void engine_kernel(EngineArgs p) {
-    __shared__ __attribute__((aligned(16))) int2 in_ring[2][kTick + 4];
-    __shared__ __attribute__((aligned(16))) int2 in_ring_cd[CD ? 2 : 1][kTick + 4];
+// K: waves per workgroup.  K = 1: every wave takes its own tickets.  K > 1 (a
+// chain workgroup, global recurrence only): the workgroup takes K consecutive
+// tickets at a time, wave w the w-th, and waves whose producer is the previous
+// wave read their top border from that wave's LDS ring.
+template <int R, bool LOCAL, bool CD, int OCC, bool PROT, int K>
+__device__ __forceinline__ void engine_body(const EngineArgs& p) {
+    static_assert(K == 1 || (!LOCAL && !PROT), "chain workgroups run the global recurrence with DNA scores");
+    __shared__ __attribute__((aligned(16))) int2 in_ring_w[K][2][kTick + 4];
+    __shared__ __attribute__((aligned(16))) int2 in_ring_cd_w[K][CD ? 2 : 1][kTick + 4];
     // Column codes of a tick: lane l reads from column col0 - l on, 18 dwords (19
     // with matrix scoring, at most index 34); the union over lanes is kBring dwords
     // from the dword holding column col0 - 63.
     constexpr int kBring = 36;
-    __shared__ uint32_t b_ring[CD ? 2 : 1][kBring];
+    __shared__ uint32_t b_ring_w[K][CD ? 2 : 1][kBring];
     // Row maxima and the pre-tick snapshot live in LDS (one column per lane) so
     // that the hot loop's registers hold only the recurrence.
     // Matrix scoring at 2 waves per SIMD keeps them in registers instead (16 of the
     // 256 VGPRs at R = 8): the LDS that frees lets the query profile fit 8 waves per CU.
     constexpr bool kRbRegs = PROT && OCC <= 2;
-    __shared__ int lds_best[kRbRegs ? 1 : R][kWave], lds_pos[kRbRegs ? 1 : R][kWave];
-    __shared__ int lds_snap[2 * R + 3][kWave];
-    __shared__ __attribute__((aligned(16))) int2 out_buf[kTick];
+    __shared__ int lds_best_w[K][kRbRegs ? 1 : R][kWave], lds_pos_w[K][kRbRegs ? 1 : R][kWave];
+    __shared__ int lds_snap_w[K][2 * R + 3][kWave];
+    __shared__ __attribute__((aligned(16))) int2 out_buf_w[K][kTick];
+    // Chain links: wave w's bottom row for wave w + 1 (column c at c mod kRing), the
+    // columns published, the columns the reader is done with, H at the band's left
+    // column; and the group's first ticket.
+    constexpr int KL = K > 1 ? K : 1;
+    __shared__ __attribute__((aligned(16))) int2 link_ring[KL][K > 1 ? kRing : 1];
+    __shared__ int link_cnt[KL], link_used[KL], link_diag[KL];
+    __shared__ uint32_t grp_first;
     // Query profile (matrix scoring): entry (class c, lane l) at dword (c * 64 + l) * kPW
     // holds s(row, c) + bias for the R rows of lane l, one byte per row (-128 for
     // rows past the matrix and for the padding class).
     extern __shared__ __attribute__((aligned(16))) uint32_t prof_lds[];
     constexpr int kPW = R > 4 ? 2 : 1;
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
-    const int lane = threadIdx.x;
+    const int lane = K > 1 ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
+    const int wv = K > 1 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave) : 0;
+    auto& in_ring = in_ring_w[wv];
+    auto& in_ring_cd = in_ring_cd_w[wv];
+    auto& b_ring = b_ring_w[wv];
+    auto& lds_best = lds_best_w[wv];
+    auto& lds_pos = lds_pos_w[wv];
+    auto& lds_snap = lds_snap_w[wv];
+    auto& out_buf = out_buf_w[wv];
 
     for (;;) {
-        uint32_t tk = 0;
-        if (lane == 0) tk = atomicAdd(p.ticket, 1u);
-        const int64_t task = (int64_t)__builtin_amdgcn_readfirstlane(tk);  // the ticket
-        if (task >= p.n_tickets) break;
+        int64_t task;
+        if constexpr (K == 1) {
+            uint32_t tk = 0;
+            if (lane == 0) tk = atomicAdd(p.ticket, 1u);
+            task = (int64_t)__builtin_amdgcn_readfirstlane(tk);  // the ticket
+            if (task >= p.n_tickets) break;
+        } else {
+            // Group start: the first ticket, and links reset (the previous group's
+            // waves all passed the closing barrier below).
+            if (threadIdx.x == 0) grp_first = atomicAdd(p.ticket, (uint32_t)K);
+            if (lane == 0) {
+                link_cnt[wv] = 0;
+                link_used[wv] = 0;
+            }
+            __syncthreads();
+            const int64_t first = (int64_t)grp_first;
+            if (first >= p.n_tickets) break;  // the same for every wave of the group
+            task = first + wv;
+        }
+        if (K == 1 || task < p.n_tickets) {
         jitter_pause(p.jitter, task, -1);
         const Ticket tkt = p.tickets[task];
         const int64_t pi = tkt.pi;
@@ -526,6 +619,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         const int32_t* prod_prog = p.progress + (prod_active ? tkt.prod : 0);
         int32_t prod_seen = 0;
         int32_t* gbest = p.gbest + pi;
+        // Chain links (wave-uniform): the producer is the previous wave of the group
+        // (read its LDS ring), the consumer is the next one (write this wave's ring).
+        const bool link_in = K > 1 && prod_active && wv > 0 && (int64_t)tkt.prod == task - 1;
+        const bool link_out = K > 1 && wv + 1 < K && tkt.cons >= 0 && (int64_t)tkt.cons == task + 1;
+        int link_room = 0;  // the reader's done count, last read (link_out)
+        // Global recurrence: the task runs only its ticks [tau_lo, tau_hi] that hold a
+        // cell of the kept band (the others would be skipped: their cells are -inf;
+        // last-row outputs outside them keep the -inf the caller filled in).  The
+        // producer's ticks bound what it writes: its columns outside
+        // [prod_first, prod_lim] read -inf (and are not waited for).
+        const bool has_out = pr.out_off >= 0 && q == pr.Q - 1;
+        // Slots of the global recurrence hold a task's written columns only, from its
+        // first (slot_first here, prod_first in the producer's slot).
+        int tau_lo = 0, tau_hi = n_ticks - 1;
+        int prod_first = 0, prod_lim = INT32_MAX - 1, slot_first = 0;
+        if constexpr (!LOCAL) {
+            band_ticks(pr, R0, c0, R, n_ticks, tau_lo, tau_hi);
+            if (tau_lo > tau_hi) {  // no tick holds a band cell (cannot happen for a ticket)
+                tau_lo = 0;
+                tau_hi = n_ticks - 1;
+            }
+            int last;
+            slot_columns(tau_lo, tau_hi, slot_first, last);
+            if (prod_active) {
+                int plo, phi;
+                band_ticks(pr, R0 - (int64_t)kWave * R, c0, R, n_ticks, plo, phi);
+                if (plo <= phi) slot_columns(plo, phi, prod_first, prod_lim);
+            }
+        }
 
         // Older tickets this one depends on.  Slot reuse: the previous owner of the
         // slot must have finished writing it, and that owner's reader (if the
@@ -556,7 +678,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             int h = NEGV, e = NEGV;
             if (row < pr.M) {
                 code = acodes[row];
-                if (band == 0) {
+                if (tau_lo > 0) {  // the ticks left of the band are not run: their cells are -inf
+                    h = kNeg;
+                    e = kNeg;
+                } else if (band == 0) {
                     h = border_h(pr.left_kind, pr.left_open, p.ext, row + 1);
                 } else if (left_active) {
                     const int2 lb = ld_shared_i2(lbuf + row);
@@ -604,10 +729,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         s.hl = s.H[R - 1];
         s.gl = NEGV;
         // H(last row of this stripe, band's left column) for the stripe below.
-        if (lane == kWave - 1) st_shared_i2(my_slot + kSlotPad - 1, make_int2(s.H[R - 1], 0));
+        if (link_out) {
+            if (lane == kWave - 1) lds_store(&link_diag[wv], s.H[R - 1]);
+            // The reader needs no column left of its first tick (less one): until it
+            // has read, the ring may hold this wave's columns up to that one + kRing - 1.
+            int clo, chi;
+            band_ticks(pr, R0 + (int64_t)kWave * R, c0, R, n_ticks, clo, chi);
+            if (lane == 0) lds_store(&link_used[wv], clo > chi ? 0 : max(0, kTick * clo - 1));
+            // The corner is written, and columns left of this wave's first tick are
+            // settled (-inf: the reader does not read them).
+            asm volatile("" ::: "memory");
+            if (lane == 0) lds_store(&link_cnt[wv], max(1, kTick * tau_lo - (kTick - 1)));
+        } else if (lane == kWave - 1) {
+            st_shared_i2(my_slot + kSlotPad - 1, make_int2(s.H[R - 1], 0));
+        }
 
         // Last-row outputs (reconstruction halves): lane and sub-row of row M-1.
-        const bool has_out = pr.out_off >= 0 && q == pr.Q - 1;
         if (has_out && band == 0 && lane == 0) {
             const int h = border_h(pr.left_kind, pr.left_open, p.ext, pr.M);
             p.out_h[pr.out_off] = h;
@@ -630,14 +767,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                 return make_int2(h, LOCAL ? 0 : kNeg);
             }
             if (!prod_active) return make_int2(kNeg, kNeg);
+            if constexpr (!LOCAL) {
+                const bool written = rel >= prod_first && rel <= prod_lim;  // else outside the producer's ticks
+                need = min(need, prod_lim + 1);
+                if (link_in) {
+                    int2 v = make_int2(kNeg, kNeg);
+                    if (written) {
+                        lds_wait_at_least(&link_cnt[wv - 1], need, prod_seen, p.abort_flag, p.wait_limit);
+                        v = link_ring[wv - 1][rel & (kRing - 1)];  // rel >= 0
+                    }
+                    asm volatile("" ::: "memory");
+                    // columns below base + 64 are read (LDS executes this wave's accesses
+                    // in order); lane 0 holds the smallest column and is active here
+                    if (lane == 0) lds_store(&link_used[wv - 1], min(base + kTick, W));
+                    return v;
+                }
+                if (!written) return make_int2(kNeg, kNeg);
+            }
             wait_at_least(prod_prog, need, prod_seen, p.abort_flag, p.wait_limit);
-            return ld_shared_i2(prod_slot + kSlotPad + rel);
+            return ld_shared_i2(prod_slot + kSlotPad + (rel - prod_first));
+        };
+        // H of the row above the stripe at band column rel (0 <= rel < W).
+        auto above_h = [&](int rel) -> int {
+            if (q == 0) {
+                if (pr.top_kind == BORDER_BUF) return p.top_h[pr.top_off + c0 + rel + 1];
+                return border_h(pr.top_kind, pr.top_open, p.ext, c0 + rel + 1);
+            }
+            if (!prod_active || rel < prod_first || rel > prod_lim) return kNeg;
+            if (link_in) {
+                lds_wait_at_least(&link_cnt[wv - 1], rel + 1, prod_seen, p.abort_flag, p.wait_limit);
+                return link_ring[wv - 1][rel & (kRing - 1)].x;
+            }
+            wait_at_least(prod_prog, rel + 1, prod_seen, p.abort_flag, p.wait_limit);
+            return ld_shared_i2(prod_slot + kSlotPad + (rel - prod_first)).x;
         };
         {
             int h_diag = 0;
-            if (q == 0) {
+            if (tau_lo > 0) {
+                // lane 0's first diagonal: the row above at the column left of the first tick
+                const int rd = kTick * tau_lo - 1;
+                h_diag = rd < W ? above_h(rd) : NEGV;
+            } else if (q == 0) {
                 if (pr.top_kind == BORDER_BUF) h_diag = p.top_h[pr.top_off + c0];
                 else h_diag = c0 == 0 ? 0 : border_h(pr.top_kind, pr.top_open, p.ext, c0);
+            } else if (link_in) {
+                lds_wait_at_least(&link_cnt[wv - 1], 1, prod_seen, p.abort_flag, p.wait_limit);
+                h_diag = lds_load(&link_diag[wv - 1]);
             } else if (prod_active) {
                 wait_at_least(prod_prog, 1, prod_seen, p.abort_flag, p.wait_limit);
                 h_diag = ld_shared_i2(prod_slot + kSlotPad - 1).x;
@@ -652,15 +827,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             } else {
                 h_diag = kNeg;
             }
-            const int2 v = fetch(0, min(kTick, W));
+            const int2 v = fetch(kTick * tau_lo, min(kTick * (tau_lo + 1), W));
             in_ring[0][lane] = v;
             if (CD) in_ring_cd[0][lane] = make_int2(v.x + lane * p.ext, v.y + lane * p.ext);
             if (CD && lane < kBring)
                 b_ring[0][lane] = reinterpret_cast<const uint32_t*>(
-                    ((uintptr_t)(bcodes + c0 - (kTick - 1)) & ~(uintptr_t)3))[lane];
+                    ((uintptr_t)(bcodes + c0 + (int64_t)kTick * tau_lo - (kTick - 1)) & ~(uintptr_t)3))[lane];
             if (lane == 0) s.hup = h_diag;
         }
-        __syncthreads();
+        wave_sync<K>();
 
         TickCtx c;
         c.prof = prof_lds + (uint32_t)lane * kPW;
@@ -703,9 +878,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         int sb_row = 0;
         int gb_pf = __hip_atomic_load(gbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-        for (int tau = 0; tau < n_ticks; ++tau) {
-            const int cur = tau & 1;
+        const int tau_end = tau_hi + 1;
+        for (int tau = tau_lo; tau < tau_end; ++tau) {
+            const int cur = (tau - tau_lo) & 1;
             prod_seen = max(prod_seen, prod_pf);
+            if (link_in) prod_seen = max(prod_seen, lds_load(&link_cnt[wv - 1]));  // an LDS read: no prefetch
             if (!LOCAL) prod_seen = __builtin_amdgcn_readfirstlane(prod_seen);
             // The next tick's inputs are loaded now, their latency hidden behind this
             // tick.  The banded global passes run as a chain of stripes each right
@@ -715,13 +892,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             // load: a late one would expose its latency).
             int2 nxt = make_int2(NEGV, NEGV);
             const int need_nxt = min(kTick * (tau + 2), W);
-            const bool nxt_now = tau + 1 < n_ticks && (LOCAL || !polls || prod_seen >= need_nxt);
+            const bool nxt_now = tau + 1 < tau_end && (LOCAL || !polls || prod_seen >= need_nxt);
             if (nxt_now) nxt = fetch(kTick * (tau + 1), need_nxt);
             uint32_t b_next = 0;  // next tick's column codes (staged at the end of this tick)
-            if (CD && tau + 1 < n_ticks && lane < kBring)
+            if (CD && tau + 1 < tau_end && lane < kBring)
                 b_next = reinterpret_cast<const uint32_t*>(
                     ((uintptr_t)(bcodes + c0 + (int64_t)kTick * (tau + 1) - (kTick - 1)) & ~(uintptr_t)3))[lane];
-            if (polls && tau + 2 < n_ticks) prod_pf = load_count(prod_prog);
+            if (polls && !link_in && tau + 2 < tau_end) prod_pf = load_count(prod_prog);
             if (has_cons) cons_pf = load_count(cons_prog);
             const uint8_t* cols = bcodes + c0 + (int64_t)kTick * tau - lane;
 
@@ -916,31 +1093,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
             }
 
             // Hand the 64 bottom-row columns of this tick to the stripe below.
-            __syncthreads();
-            {
+            wave_sync<K>();
+            if (link_out) {
+                // the ring slots of these columns must be read: the reader is done
+                // with every column below kTick * tau - kRing + 1
+                lds_wait_at_least(&link_used[wv], kTick * tau - kRing + 1, link_room, p.abort_flag, p.wait_limit);
                 const int rel = kTick * tau - (kTick - 1) + lane;
                 int2 o = out_buf[lane];
                 if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext
                     o.x -= (lane - (kTick - 1)) * p.ext;
                     o.y -= (lane - (kTick - 1)) * p.ext;
                 }
-                if (rel >= 0) st_shared_i2(my_slot + kSlotPad + rel, o);
+                if (rel >= 0) link_ring[wv][rel & (kRing - 1)] = o;
+                jitter_pause(p.jitter, task, tau);
+                asm volatile("" ::: "memory");
+                if (lane == 0) lds_store(&link_cnt[wv], min(kTick * tau + 1, W));
+            } else {
+                {
+                    const int rel = kTick * tau - (kTick - 1) + lane;
+                    int2 o = out_buf[lane];
+                    if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext
+                        o.x -= (lane - (kTick - 1)) * p.ext;
+                        o.y -= (lane - (kTick - 1)) * p.ext;
+                    }
+                    // (global recurrence: only a task with a consumer, only its columns)
+                    if (rel >= 0 && (LOCAL || tkt.cons >= 0)) st_shared_i2(my_slot + kSlotPad + (rel - slot_first), o);
+                }
+                jitter_pause(p.jitter, task, tau);
+                publish_count(p.progress + task, min(kTick * tau + 1, W));
             }
-            jitter_pause(p.jitter, task, tau);
-            publish_count(p.progress + task, min(kTick * tau + 1, W));
             if (has_cons) {
                 const int32_t cs = __builtin_amdgcn_readfirstlane(cons_pf);
                 if (cs > 0 && min(kTick * tau + 1, W) - cs <= 4 * kTick) __builtin_amdgcn_s_setprio(2);
                 else __builtin_amdgcn_s_setprio(0);
             }
-            if (!LOCAL && tau + 1 < n_ticks && !nxt_now) {
+            if (!LOCAL && tau + 1 < tau_end && !nxt_now) {
                 prod_seen = max(prod_seen, prod_pf);
                 nxt = fetch(kTick * (tau + 1), need_nxt);
             }
             in_ring[cur ^ 1][lane] = nxt;
             if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + lane * p.ext, nxt.y + lane * p.ext);
             if (CD && lane < kBring) b_ring[cur ^ 1][lane] = b_next;
-            __syncthreads();
+            wave_sync<K>();
+        }
+        if constexpr (!LOCAL) {
+            // The ticks not run count as skipped; a lane whose capture column lies in one
+            // of them hands -inf to the next band.
+            pruned += (unsigned long long)(n_ticks - (tau_end - tau_lo)) * kTick * kWave * R;
+            const int tc = (W - 1 + lane) / kTick;
+            if (capture && (tc < tau_lo || tc >= tau_end)) {
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (k < M_rows) st_shared_i2(lbuf + row0 + k, make_int2(kNeg, kNeg));
+            }
         }
 
         // Task record: the stripe's best value, its smallest row, that row's first column.
@@ -981,7 +1186,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
         }
         publish_count(p.progress + task, kDone);
         __builtin_amdgcn_s_setprio(0);
+        }
+        if constexpr (K > 1) __syncthreads();  // group end: every wave is done with the links
     }
+}
+
+template <int R, bool LOCAL, bool CD, int OCC, bool PROT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void engine_kernel(EngineArgs p) {
+    engine_body<R, LOCAL, CD, OCC, PROT, 1>(p);
+}
+
+// The banded global passes (reverse pass, reconstruction halves) with K waves per
+// workgroup linked through LDS; DNA scores in the column-shifted domain.
+template <int R, int K, int OCC>
+__global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(OCC))) void chain_kernel(EngineArgs p) {
+    engine_body<R, false, true, OCC, false, K>(p);
 }
 
 // ------------------------------------------------------------------------ small kernels
@@ -1161,15 +1380,28 @@ static void launch_variant(const EngineArgs& args, int R, int occ, dim3 g, hipSt
     }
     if (R == 6 && occ <= 2) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 2, false>), g, b, 0, st, args);
     else if (R == 6) hipLaunchKernelGGL((engine_kernel<6, LOCAL, CD, 3, false>), g, b, 0, st, args);
+    else if (R == 4 && !LOCAL && occ <= 2) hipLaunchKernelGGL((engine_kernel<4, false, CD, 2, false>), g, b, 0, st, args);
     else if (R == 4) hipLaunchKernelGGL((engine_kernel<4, LOCAL, CD, 4, false>), g, b, 0, st, args);
     else if (occ <= 2) hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 2, false>), g, b, 0, st, args);
     else hipLaunchKernelGGL((engine_kernel<8, LOCAL, CD, 3, false>), g, b, 0, st, args);
 }
 
+bool chain_variant(int rows_per_lane, bool local, bool cd, int n_class, int chain) {
+    return !local && cd && n_class == 0 && rows_per_lane == 4 && (chain == 4 || chain == 8);
+}
+
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
-                         hipStream_t st) {
+                         int chain, hipStream_t st) {
     if (rows_per_lane != 4 && rows_per_lane != 6 && rows_per_lane != 8) return hipErrorInvalidValue;
     if (args.sub.n_class < 0 || args.sub.n_class > kMaxClasses) return hipErrorInvalidValue;
+    if (grid < 1) return hipErrorInvalidValue;
+    if (chain_variant(rows_per_lane, local, cd, args.sub.n_class, chain)) {
+        // groups of `chain` waves; each group takes `chain` tickets at a time
+        const dim3 g((unsigned)((grid + chain - 1) / chain)), b((unsigned)(kWave * chain));
+        if (chain == 8) hipLaunchKernelGGL((chain_kernel<4, 8, 2>), g, b, 0, st, args);
+        else hipLaunchKernelGGL((chain_kernel<4, 4, 2>), g, b, 0, st, args);
+        return hipGetLastError();
+    }
     const int occ = (waves_per_cu + 3) / 4;  // waves per SIMD (4 SIMDs per CU)
     const dim3 g(grid);
     if (local && cd) launch_variant<true, true>(args, rows_per_lane, occ, g, st);

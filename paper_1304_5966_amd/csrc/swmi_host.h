@@ -80,7 +80,8 @@ struct ProbSpec {
 struct EnginePlan {
     int R = 8;
     int wpc = 8;  // resident stripe waves per CU the launch is sized for
-    int grid = 1;
+    int grid = 1;   // waves
+    int chain = 1;  // waves per workgroup of a chain launch (1: none); the ticket order keeps runs of `chain`
     bool local = true;
     int64_t n_probs = 0, n_tasks = 0, n_tickets = 0, nslot = 2, slot_stride = 0, lbuf_rows = 0;
     std::vector<Prob> probs;

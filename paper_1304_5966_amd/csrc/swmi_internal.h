@@ -106,6 +106,29 @@ __host__ __device__ inline bool task_in_band(const Prob& pr, int64_t band, int64
     return !(dmax < pr.d_lo || dmin > pr.d_hi);
 }
 
+// Ticks [lo, hi] of a task (stripe rows from R0, band columns from c0, n_ticks
+// ticks) that hold a cell of the kept diagonal band: tick tau covers diagonals
+// from c0 + 64 tau - R0 - 64 R - 62 to c0 + 64 tau + 63 - R0 (the range the tick
+// loop's band test checks).  Unbanded: every tick.  lo > hi: none.
+__host__ __device__ inline void band_ticks(const Prob& pr, int64_t R0, int64_t c0, int R, int n_ticks, int& lo,
+                                           int& hi) {
+    const int64_t a = pr.d_lo - (kTick - 1) + R0 - c0;                       // 64 tau >= a
+    const int64_t b = pr.d_hi + R0 + (int64_t)kWave * R + (kTick - 2) - c0;  // 64 tau <= b
+    const int64_t l = a <= 0 ? 0 : (a + kTick - 1) / kTick;
+    const int64_t h = b < 0 ? -1 : b / kTick;
+    lo = (int)(l < n_ticks ? l : n_ticks);
+    hi = (int)(h < n_ticks - 1 ? h : n_ticks - 1);
+}
+
+// Columns a task of the global recurrence writes to its slot (for its consumer):
+// from its first tick's first output column to its last tick's last; slots are
+// indexed from the first.
+__host__ __device__ inline void slot_columns(int lo, int hi, int& first, int& last) {
+    first = kTick * lo - (kTick - 1);
+    if (first < 0) first = 0;
+    last = kTick * hi;
+}
+
 struct EngineArgs {
     const Ticket* tickets;
     const Prob* probs;
@@ -173,8 +196,13 @@ hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const 
 // SIMD (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
 // Matrix scoring (args.sub.n_class > 0) runs the same shapes; its launches take
 // n_class * 64 * (4 or 8) bytes of dynamic LDS for the stripe's query profile.
+// grid: waves.  chain (4 or 8; 1: off): where chain_variant() holds, the launch runs
+// workgroups of `chain` waves that take `chain` consecutive tickets at a time and
+// link consecutive stripes through LDS (the ticket table must then keep each
+// problem's stripes in runs of `chain` tickets to profit; any valid table is correct).
+bool chain_variant(int rows_per_lane, bool local, bool cd, int n_class, int chain);
 hipError_t launch_engine(const EngineArgs& args, int rows_per_lane, int waves_per_cu, bool local, bool cd, int grid,
-                         hipStream_t st);
+                         int chain, hipStream_t st);
 // rows_per_lane: the launch's R (records of tasks outside a kept band are skipped).
 hipError_t launch_reduce(const TaskRec* recs, const Prob* probs, int64_t n_probs, int rows_per_lane, ScoreOut* out,
                          const int32_t* gbest, const unsigned long long* pruned, const int32_t* abort_flag,

@@ -106,3 +106,27 @@ def test_align_config1(ctx, orc):
     got = ctx.align(a, b)
     exp = orc.sw_align(a, b)
     assert _key(got) == (exp.score, exp.start_a, exp.start_b, exp.end_a, exp.end_b, exp.cigar)
+
+
+_CHAIN_CASES = [(12000, 11000, 0.08, {}), (9000, 15000, 0.12, {}), (14000, 13000, 0.05, dict(band_width=640)),
+                (6000, 5800, 0.2, dict(band_width=1280)), (7000, 6500, 0.1, dict(waves_per_cu=1))]
+_chain_expected = {}
+
+
+@pytest.mark.parametrize("chain", ["1", "4", "8"])
+def test_align_chain_workgroups(ctx, orc, monkeypatch, chain):
+    """The banded global passes (start pass, reconstruction levels) with K waves per
+    workgroup on consecutive stripes, linked through LDS (K = 4, 8), and with one wave
+    per workgroup (K = 1), against the oracle: long pairs (long chains of stripes),
+    narrow column bands (chains cut at band edges, left-boundary hand-offs inside a
+    group) and a small grid (slot reuse, few resident groups)."""
+    monkeypatch.setenv("SWMI_CHAIN_WAVES", chain)
+    for i, (la, lb, div, opts) in enumerate(_CHAIN_CASES):
+        p = synth.homologous_pair(900 + i, la, lb, div)
+        a, b = p.a.tobytes(), p.b.tobytes()
+        if i not in _chain_expected:
+            e = orc.sw_align(a, b)
+            _chain_expected[i] = (e.score, e.start_a, e.start_b, e.end_a, e.end_b, e.cigar)
+        _case(f"chain {chain}: align {la}x{lb} div={div} {opts}")
+        got = ctx.align(a, b, rows_per_lane=4, **opts)
+        assert _key(got) == _chain_expected[i], (chain, opts)
