@@ -109,3 +109,32 @@ def test_wait_limit_abort_path(ctx, orc, monkeypatch):
         assert ctx.score(a, b).key() == exp
         assert ctx.align(a, b).score == exp[0]
     assert aborted > 0
+
+
+def test_wait_limit_abort_path_chain_workgroups(ctx, orc, monkeypatch):
+    """The same failure path in the banded start pass, which runs in chain workgroups
+    (waves of a workgroup linked through LDS, with their own bounded waits): under a
+    one-microsecond limit and perturbed schedules a launch either gives the exact start
+    point or ends with an internal error; the default limit gives the exact result."""
+    from paper_1304_5966_amd import swmi
+    p = synth.homologous_pair(37, 9000, 8600, 0.08)
+    a, b = p.a.tobytes(), p.b.tobytes()
+    exp = orc.sw_align(a, b)
+    aborted = 0
+    for seed in (3, 4, 5):
+        monkeypatch.setenv("SWMI_WAIT_LIMIT_US", "1")
+        monkeypatch.setenv("SWMI_SCHEDULE_JITTER", str(seed))
+        _case(f"start pass, wait limit 1 us, jitter seed {seed}")
+        try:
+            st = ctx.start(a, b, exp.score, exp.end_a, exp.end_b)
+            assert st == (exp.start_a, exp.start_b)
+        except swmi.SwError as e:
+            assert e.status == swmi.SW_EINTERNAL and "timed out" in str(e), e
+            aborted += 1
+        monkeypatch.delenv("SWMI_WAIT_LIMIT_US")
+        monkeypatch.delenv("SWMI_SCHEDULE_JITTER")
+        _case("start pass and alignment at the default limit")
+        assert ctx.start(a, b, exp.score, exp.end_a, exp.end_b) == (exp.start_a, exp.start_b)
+        al = ctx.align(a, b)
+        assert (al.start_a, al.start_b, al.cigar) == (exp.start_a, exp.start_b, exp.cigar)
+    assert aborted > 0
