@@ -16,6 +16,8 @@ timed on a bounded crop of the same pair.
 ``--only batched|learned|align|genome|protein`` runs one leg alone and prints its JSON
 (for profiling a leg by itself).  The genome leg is the score pass of the
 32 Mbp x 28 Mbp genome-scale pair with running-best pruning, in row slabs.
+``--time-budget S`` (default 540 s) bounds the whole run: an extra leg whose
+usual duration no longer fits is skipped and named as skipped in the line.
 """
 from __future__ import annotations
 
@@ -134,10 +136,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--seq-sample", type=int, default=2000)
-    ap.add_argument("--no-genome", action="store_true", help="skip the genome-scale leg (about 4.5 minutes)")
+    ap.add_argument("--no-genome", action="store_true", help="skip the genome-scale leg (about 5 minutes)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds the whole run may take: an extra leg whose usual duration no longer fits "
+                         "is skipped and reported as such (the CPU baseline always runs)")
     ap.add_argument("--only", choices=("batched", "learned", "align", "genome", "protein"), default=None,
                     help="run one extra leg alone and print its JSON object")
     args = ap.parse_args()
+    t_run = time.perf_counter()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the score pass is "
               f"not sharded across GPUs)", file=sys.stderr)
@@ -247,16 +253,35 @@ def main():
         assert r.key() == score, (r, score)
         line["pruned_best"] = {"gcups_eff": round(cells / dt / 1e9, 2), "ms": round(dt * 1000, 3),
                                "cells_computed_frac": round(r.cells_computed / cells, 4)}
-        line["alignment"] = alignment_leg(ctx, torch, pair, d_a, d_b, opts)
-        line["batched"] = batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)
-        line["learned_pruned"] = learned_leg(ctx, torch, swmi, synth, args.learned_pairs)
-        line["protein"] = protein_leg(ctx, torch, swmi, synth)
-        if not args.no_genome:
-            line["genome_scale"] = genome_leg(ctx, torch, swmi, synth)
+        legs = [("alignment", lambda: alignment_leg(ctx, torch, pair, d_a, d_b, opts)),
+                ("batched", lambda: batched_leg(ctx, torch, swmi, synth, args.seq_sample, not args.no_tune)),
+                ("learned_pruned", lambda: learned_leg(ctx, torch, swmi, synth, args.learned_pairs)),
+                ("protein", lambda: protein_leg(ctx, torch, swmi, synth))]
+        for key, run in legs:
+            line[key] = run_leg(key, run, t_run, args.time_budget)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(pair)
+    if not (args.no_extra or args.no_genome):
+        line["genome_scale"] = run_leg("genome_scale", lambda: genome_leg(ctx, torch, swmi, synth),
+                                       t_run, args.time_budget)
     print(json.dumps(line), flush=True)
+
+
+# Usual wall-clock seconds of each extra leg on one MI355X (pair generation included),
+# with some margin: a leg runs only if this much time is left in the run's budget.
+LEG_SECONDS = {"alignment": 30, "batched": 75, "learned_pruned": 90, "protein": 45, "genome_scale": 320}
+
+
+def run_leg(key, run, t_run, budget):
+    """Run one extra leg if its usual duration fits in what is left of the time budget."""
+    left = budget - (time.perf_counter() - t_run)
+    if LEG_SECONDS[key] > left:
+        log(f"{key} leg skipped: {left:.0f} s left of the {budget:.0f} s budget, the leg takes about "
+            f"{LEG_SECONDS[key]} s")
+        return {"skipped": f"time budget: {left:.0f} s left of {budget:.0f} s, the leg takes about "
+                           f"{LEG_SECONDS[key]} s (run it with --only or a larger --time-budget)"}
+    return run()
 
 
 def alignment_leg(ctx, torch, pair, d_a, d_b, opts):

@@ -40,3 +40,17 @@ def test_counters_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
     c = bench.profiled_counters()
     assert c["match"] is False
     assert bench.roofline(2.0e12, 1.0, c)["traffic"] is None
+
+
+def test_extra_leg_skipped_when_the_time_budget_is_spent():
+    import time
+    ran = []
+    t0 = time.perf_counter()
+    out = bench.run_leg("genome_scale", lambda: ran.append(1) or {"ok": 1}, t0, budget=100.0)
+    assert ran == [] and "time budget" in out["skipped"]
+    out = bench.run_leg("alignment", lambda: ran.append(1) or {"ok": 1}, t0, budget=1000.0)
+    assert ran == [1] and out == {"ok": 1}
+    # every leg of the default run has an estimate, and together they fit the default budget
+    # when the genome leg is left out of it
+    assert set(bench.LEG_SECONDS) == {"alignment", "batched", "learned_pruned", "protein", "genome_scale"}
+    assert sum(v for k, v in bench.LEG_SECONDS.items() if k != "genome_scale") < 540
