@@ -672,7 +672,7 @@ sw_status swmi::launch_engine_kernels(sw_context* ctx, const EnginePlan& plan, c
     for (const Prob& pr : plan.probs)
         if (pr.top_kind == BORDER_BUF && (!top_h || !top_f || pr.top_off < 0))
             return fail(SW_EINTERNAL, "engine plan: a buffer top border without its row");
-    const bool cd = sc->match + sc->gap_extend <= 127;
+    const bool cd = sc->match + cd_bias_ext(plan.R) * sc->gap_extend <= 127;
     HIP_TRY(launch_engine(a, plan.R, plan.wpc, plan.local, cd, plan.grid, plan.chain, st));
     HIP_TRY(launch_reduce(a.recs, a.probs, plan.n_probs, plan.R, (ScoreOut*)(base + plan.off_outs), a.gbest,
                           a.pruned, a.abort_flag, st));

@@ -313,7 +313,8 @@ constexpr int kRun = 0, kTrack = 1, kExact = 2;
 //  SLOW: per-step predicates -- lanes left of the band's first column hold
 //        their state (tick 0); H,E at the band's last column go to lbuf; the
 //        last matrix row's H and F go to out_h/out_f.
-//  CD:   the row tables hold s + ext (the shifted-domain tables); subtract it.
+//  CD:   the row tables hold the shifted-domain scores (s + ext, or s + 2 ext
+//        where the row shift is on); subtract the bias.
 template <int R, bool LOCAL, int MODE, bool SLOW, bool CD, bool PROT>
 __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const uint8_t* first,
                                          const TickCtx& c, const bool (&want)[R]) {
@@ -331,7 +332,7 @@ __device__ __forceinline__ void run_tick(WaveState<R>& s, RowBest<R>& rb, const 
     // lane 0's inputs are read one 4-step group ahead (the ring holds 64 + 4 entries)
     const int4* in4 = reinterpret_cast<const int4*>(c.in);
     int4 nx0 = in4[0], nx1 = in4[1];
-    const int bias = CD ? c.ext : 0;
+    const int bias = CD ? cd_bias_ext(R) * c.ext : 0;
     constexpr int kUnroll = (SLOW || REPLAY) ? 1 : 2;  // the hot path renames its carried registers
 #pragma unroll kUnroll
     for (int g = 0; g < kTick / 4; ++g) {
@@ -521,6 +522,121 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
     return TRACKMAX ? acc - back : kNeg;
 }
 
+// Shifted tick in the row-and-column-shifted domain (R = 4 or 8 rows per lane).
+// Cell (stripe row r, tick column t) carries (r + t) * ext on top of its value, so
+// the extension of E along a row and of F down a column are both absorbed:
+// E' = max(E', H' - g) and F' = max(F', H' - g) with g = open - ext, one maximum
+// each and the same H' - g for both.  The diagonal step moves one row and one
+// column, so the score bytes hold s + 2 ext.  Lane l's rows are stripe rows lR..
+// lR + R - 1, so the values passed between lanes need no adjustment; lane 0's H
+// from the row above enters with -ext (stripe row -1), and lane 63's outputs carry
+// rows 64R - 1 (H) and 64R (F), which the caller removes.  The local zero of row k
+// at step m is the row-0 zero of step m + k: the R zeros in use sit in a window of
+// registers, and each step advances the one it has finished with by R steps.  The
+// window's index is a compile-time constant because R divides the 8 steps of the
+// unrolled body.  The running maximum compares H' - k ext, the row-0 domain.
+template <int R, bool TRACKMAX, bool LOCAL, bool PROT>
+__device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
+    static_assert(8 % R == 0, "the zero window needs R to divide the 8 steps of the unrolled body");
+    const int ext = c.ext, g = c.open - c.ext;
+    const int rbase = c.lane * R;                // stripe row of the lane's first row
+    const int off = (rbase - c.lane - 1) * ext;  // the carried state belongs to step -1
+    int HA[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        s.H[k] += off + k * ext;
+        s.E[k] += off + k * ext;
+        HA[k] = s.H[k] - g;
+    }
+    s.hup += off - ext;            // stripe row rbase - 1
+    s.hl += off + (R - 1) * ext;   // stripe row rbase + R - 1
+    s.gl += off + R * ext;         // F entering stripe row rbase + R
+    int zw[R];                     // zw[j]: zero of row 0 at the window's step congruent to j mod R
+#pragma unroll
+    for (int j = 0; j < R; ++j) zw[j] = (rbase - c.lane + j) * ext;
+    const int zstep = R * ext;
+    int acc = kNeg;        // max over the steps so far of (H - zero of row 0), plus the current zero
+    int ohl = 0, ogl = 0;  // lane 63's output of the even step, stored with the odd one
+    const uint32_t* src = c.bring + ((((uintptr_t)first & ~(uintptr_t)3) - c.bbase) >> 2);
+    const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
+    uint32_t lo = src[0], hi = src[1];
+    const int4* in4 = reinterpret_cast<const int4*>(c.in_cd);
+    int4 nx0 = in4[0], nx1 = in4[1];
+    uint32_t hi2 = PROT ? src[2] : 0;
+    ScoreGroup<R, PROT> sg_next;
+    if (PROT) sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
+    for (int g2 = 0; g2 < kTick / 8; ++g2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gi = 2 * g2 + h;
+            const uint32_t cw = __builtin_amdgcn_alignbyte(hi, lo, sh);
+            lo = hi;
+            if (PROT) {
+                hi = hi2;
+                hi2 = src[gi + 3];
+            } else {
+                hi = src[gi + 2];
+            }
+            const int2 ins[4] = {make_int2(nx0.x, nx0.y), make_int2(nx0.z, nx0.w), make_int2(nx1.x, nx1.y),
+                                 make_int2(nx1.z, nx1.w)};
+            nx0 = in4[2 * gi + 2];
+            nx1 = in4[2 * gi + 3];
+            ScoreGroup<R, PROT> sg;
+            if (PROT) {
+                sg = sg_next;
+                sg_next.load(s.T, __builtin_amdgcn_alignbyte(hi, lo, sh), c);
+            } else {
+                sg.load(s.T, cw, c);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * gi + i;
+                const int j0 = (4 * h + i) % R;  // m mod R
+                const int upH = dpp_shr1(ins[i].x, s.hl);
+                const int upG = dpp_shr1(ins[i].y, s.gl);
+                int diag = s.hup;
+                s.hup = upH;
+                int F = upG;
+                if (TRACKMAX) acc += ext;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int Hd = diag + sg.get(i, k);
+                    const int En = LOCAL ? max(max(s.E[k], HA[k]), zw[(j0 + k) % R]) : max(s.E[k], HA[k]);
+                    const int Hn = max(max(Hd, En), F);
+                    const int HAn = Hn - g;
+                    F = max(F, HAn);
+                    diag = s.H[k];
+                    s.H[k] = Hn;
+                    s.E[k] = En;
+                    HA[k] = HAn;
+                    if (TRACKMAX) acc = max(acc, Hn - k * ext);
+                }
+                if (LOCAL) zw[j0] += zstep;
+                s.hl = s.H[R - 1];
+                s.gl = F;
+                if (i & 1) {
+                    if (c.lane == kWave - 1)
+                        *reinterpret_cast<int4*>(c.out + m - 1) = make_int4(ohl, ogl, s.hl, s.gl);
+                } else {
+                    ohl = s.hl;
+                    ogl = s.gl;
+                }
+            }
+        }
+    }
+    const int back = (kTick - 1 - c.lane) * ext;  // column shift of step 63
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        s.H[k] -= back + (rbase + k) * ext;
+        s.E[k] -= back + (rbase + k) * ext;
+        s.HA[k] = s.H[k] - c.open;
+    }
+    s.hup -= back + (rbase - 1) * ext;
+    s.hl -= back + (rbase + R - 1) * ext;
+    s.gl -= back + (rbase + R) * ext;
+    return TRACKMAX ? acc - back - rbase * ext : kNeg;
+}
+
 // CD: fast ticks run in the column-shifted domain (run_tick_cd); needs
 // match + ext <= 127 so that s + ext fits the score bytes.
 // OCC: resident waves per SIMD the register allocation is sized for
@@ -562,6 +678,7 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
     extern __shared__ __attribute__((aligned(16))) uint32_t prof_lds[];
     constexpr int kPW = R > 4 ? 2 : 1;
     constexpr int NEGV = LOCAL ? 0 : kNeg;  // value of an unreachable cell in the recurrence in use
+    constexpr int kRs = (CD && cd_row_shift(R)) ? 1 : 0;  // shifted ticks also shift by the stripe row
     const int lane = K > 1 ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
     const int wv = K > 1 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave) : 0;
     auto& in_ring = in_ring_w[wv];
@@ -692,7 +809,7 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
                     e = kNeg;
                 }
             }
-            s.T[k] = PROT ? (uint32_t)code : row_table(code, p.match, p.mismatch, CD ? p.ext : 0);
+            s.T[k] = PROT ? (uint32_t)code : row_table(code, p.match, p.mismatch, CD ? cd_bias_ext(R) * p.ext : 0);
             s.H[k] = h;
             s.E[k] = e;
             s.HA[k] = h - p.open;
@@ -708,7 +825,7 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
             // This task's query profile.  Each lane writes and later reads only its
             // own entries, so no barrier is needed; the row codes were parked in T.
             const int nc = p.sub.n_class;
-            const int bias = CD ? p.ext : 0;
+            const int bias = CD ? cd_bias_ext(R) * p.ext : 0;
             for (int cl = 0; cl < nc; ++cl) {
                 uint32_t w[kPW];
 #pragma unroll
@@ -829,7 +946,7 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
             }
             const int2 v = fetch(kTick * tau_lo, min(kTick * (tau_lo + 1), W));
             in_ring[0][lane] = v;
-            if (CD) in_ring_cd[0][lane] = make_int2(v.x + lane * p.ext, v.y + lane * p.ext);
+            if (CD) in_ring_cd[0][lane] = make_int2(v.x + (lane - kRs) * p.ext, v.y + lane * p.ext);
             if (CD && lane < kBring)
                 b_ring[0][lane] = reinterpret_cast<const uint32_t*>(
                     ((uintptr_t)(bcodes + c0 + (int64_t)kTick * tau_lo - (kTick - 1)) & ~(uintptr_t)3))[lane];
@@ -1028,8 +1145,14 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
                 out_buf[lane] = make_int2(NEGV, NEGV);
             } else if (cd_tick) {
                 if (track_max) snapshot();  // without the running maximum there is no replay
-                const int tmax = track_max ? run_tick_cd<R, true, LOCAL, PROT>(s, cols, c)
-                                           : run_tick_cd<R, false, LOCAL, PROT>(s, cols, c);
+                int tmax;
+                if constexpr (kRs) {
+                    tmax = track_max ? run_tick_rs<R, true, LOCAL, PROT>(s, cols, c)
+                                     : run_tick_rs<R, false, LOCAL, PROT>(s, cols, c);
+                } else {
+                    tmax = track_max ? run_tick_cd<R, true, LOCAL, PROT>(s, cols, c)
+                                     : run_tick_cd<R, false, LOCAL, PROT>(s, cols, c);
+                }
                 if (pr.target > 0 && track_max) {
                     // Under an external target, ticks below it are not replayed; keep the
                     // largest H seen in the running best (a valid lower bound of the optimum)
@@ -1100,9 +1223,9 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
                 lds_wait_at_least(&link_used[wv], kTick * tau - kRing + 1, link_room, p.abort_flag, p.wait_limit);
                 const int rel = kTick * tau - (kTick - 1) + lane;
                 int2 o = out_buf[lane];
-                if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext
-                    o.x -= (lane - (kTick - 1)) * p.ext;
-                    o.y -= (lane - (kTick - 1)) * p.ext;
+                if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext, plus its row shift
+                    o.x -= (lane - (kTick - 1) + kRs * (kWave * R - 1)) * p.ext;
+                    o.y -= (lane - (kTick - 1) + kRs * kWave * R) * p.ext;
                 }
                 if (rel >= 0) link_ring[wv][rel & (kRing - 1)] = o;
                 jitter_pause(p.jitter, task, tau);
@@ -1112,9 +1235,9 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
                 {
                     const int rel = kTick * tau - (kTick - 1) + lane;
                     int2 o = out_buf[lane];
-                    if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext
-                        o.x -= (lane - (kTick - 1)) * p.ext;
-                        o.y -= (lane - (kTick - 1)) * p.ext;
+                    if (cd_tick) {  // lane 63's step `lane` carried (lane - 63) * ext, plus its row shift
+                        o.x -= (lane - (kTick - 1) + kRs * (kWave * R - 1)) * p.ext;
+                        o.y -= (lane - (kTick - 1) + kRs * kWave * R) * p.ext;
                     }
                     // (global recurrence: only a task with a consumer, only its columns)
                     if (rel >= 0 && (LOCAL || tkt.cons >= 0)) st_shared_i2(my_slot + kSlotPad + (rel - slot_first), o);
@@ -1132,7 +1255,7 @@ __device__ __forceinline__ void engine_body(const EngineArgs& p) {
                 nxt = fetch(kTick * (tau + 1), need_nxt);
             }
             in_ring[cur ^ 1][lane] = nxt;
-            if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + lane * p.ext, nxt.y + lane * p.ext);
+            if (CD) in_ring_cd[cur ^ 1][lane] = make_int2(nxt.x + (lane - kRs) * p.ext, nxt.y + lane * p.ext);
             if (CD && lane < kBring) b_ring[cur ^ 1][lane] = b_next;
             wave_sync<K>();
         }

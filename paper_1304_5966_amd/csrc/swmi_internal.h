@@ -17,6 +17,12 @@ constexpr uint32_t kPadTable = 0x80808080u;
 constexpr int32_t kNeg = -(1 << 30);  // minus infinity of the global recurrence
 constexpr int64_t kNoBand = (int64_t)1 << 62;
 
+// Shifted ticks of R = 4 and 8 rows per lane shift every cell by its stripe row as
+// well as its tick column (times gap_extend), so their score bytes hold s + 2 ext;
+// R = 6 shifts by the column only (s + ext).  The bytes must stay within int8.
+constexpr bool cd_row_shift(int rows_per_lane) { return rows_per_lane == 4 || rows_per_lane == 8; }
+constexpr int cd_bias_ext(int rows_per_lane) { return cd_row_shift(rows_per_lane) ? 2 : 1; }
+
 // Substitution-matrix scoring (protein alignment).  Letters are encoded as their
 // index in the matrix alphabet; the class after the last letter is the padding
 // class, whose row and column score -128 like kPadCode's.
