@@ -87,12 +87,14 @@ def roofline(cells, kernel_s, counters):
         out.update({"achieved": None, "frac": None, "traffic": None, "valu_per_cell": None,
                     "counters": "no counter summary"})
         return out
+    if not counters["match"]:  # counted on another kernel source: no instruction count, no traffic
+        out.update({"achieved": None, "frac": None, "traffic": None, "valu_per_cell": None,
+                    "counters": "profiles/engine_kernel_5Mx4M_counters.md (taken on another kernel source)"})
+        return out
     issued = counters["valu_per_cell"] * cells / kernel_s
     out.update({"achieved": round(issued / 1e12, 3), "frac": round(issued / VALU_PEAK, 4),
-                "valu_per_cell": round(counters["valu_per_cell"], 3),
-                "traffic": counters["traffic"] if counters["match"] else None,
-                "counters": "profiles/engine_kernel_5Mx4M_counters.md" +
-                            ("" if counters["match"] else " (taken on another kernel source)")})
+                "valu_per_cell": round(counters["valu_per_cell"], 3), "traffic": counters["traffic"],
+                "counters": "profiles/engine_kernel_5Mx4M_counters.md"})
     return out
 
 

@@ -39,7 +39,15 @@ def test_counters_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
     src.write_bytes(b"// kernel v2\n")  # source changed since the counters were taken
     c = bench.profiled_counters()
     assert c["match"] is False
-    assert bench.roofline(2.0e12, 1.0, c)["traffic"] is None
+    r = bench.roofline(2.0e12, 1.0, c)
+    # neither the traffic nor an instruction count of another source is reported
+    assert r["traffic"] is None and r["frac"] is None and r["achieved"] is None and r["valu_per_cell"] is None
+    assert r["algorithmic_tops"] == 20.0
+
+
+def test_committed_counters_match_the_kernel_source():
+    c = bench.profiled_counters()
+    assert c is not None and c["match"], "profiles/engine_kernel_5Mx4M_counters.md is stale: re-take the counters"
 
 
 def test_extra_leg_skipped_when_the_time_budget_is_spent():
