@@ -534,7 +534,10 @@ __device__ __forceinline__ int run_tick_cd(WaveState<R>& s, const uint8_t* first
 // at step m is the row-0 zero of step m + k: the R zeros in use sit in a window of
 // registers, and each step advances the one it has finished with by R steps.  The
 // window's index is a compile-time constant because R divides the 8 steps of the
-// unrolled body.  The running maximum compares H' - k ext, the row-0 domain.
+// unrolled body.  The running maximum uses the same fact: every cell of one
+// anti-diagonal carries the same shift, so each cell is folded into the maximum of
+// its anti-diagonal, kept in a second window of R registers that advances with the
+// first; the shifts are taken off once, after the tick.
 template <int R, bool TRACKMAX, bool LOCAL, bool PROT>
 __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first, const TickCtx& c) {
     static_assert(8 % R == 0, "the zero window needs R to divide the 8 steps of the unrolled body");
@@ -555,7 +558,9 @@ __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first
 #pragma unroll
     for (int j = 0; j < R; ++j) zw[j] = (rbase - c.lane + j) * ext;
     const int zstep = R * ext;
-    int acc = kNeg;        // max over the steps so far of (H - zero of row 0), plus the current zero
+    int aw[R];             // aw[j]: largest shifted H on the window's anti-diagonal congruent to j mod R
+#pragma unroll
+    for (int j = 0; j < R; ++j) aw[j] = kNeg;
     int ohl = 0, ogl = 0;  // lane 63's output of the even step, stored with the odd one
     const uint32_t* src = c.bring + ((((uintptr_t)first & ~(uintptr_t)3) - c.bbase) >> 2);
     const uint32_t sh = (uint32_t)((uintptr_t)first & 3);
@@ -597,7 +602,6 @@ __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first
                 int diag = s.hup;
                 s.hup = upH;
                 int F = upG;
-                if (TRACKMAX) acc += ext;
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     const int Hd = diag + sg.get(i, k);
@@ -609,9 +613,11 @@ __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first
                     s.H[k] = Hn;
                     s.E[k] = En;
                     HA[k] = HAn;
-                    if (TRACKMAX) acc = max(acc, Hn - k * ext);
+                    if (TRACKMAX) aw[(j0 + k) % R] = max(aw[(j0 + k) % R], Hn);
                 }
+                // anti-diagonal m is complete: its slot moves on to anti-diagonal m + R
                 if (LOCAL) zw[j0] += zstep;
+                if (TRACKMAX) aw[j0] += zstep;
                 s.hl = s.H[R - 1];
                 s.gl = F;
                 if (i & 1) {
@@ -634,7 +640,13 @@ __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first
     s.hup -= back + (rbase - 1) * ext;
     s.hl -= back + (rbase + R - 1) * ext;
     s.gl -= back + (rbase + R) * ext;
-    return TRACKMAX ? acc - back - rbase * ext : kNeg;
+    if (!TRACKMAX) return kNeg;
+    // after step 63 slot j holds anti-diagonal 64 + j (R divides 64), whose cells
+    // carry (rbase - lane + 64 + j) * ext
+    int tmax = kNeg;
+#pragma unroll
+    for (int j = 0; j < R; ++j) tmax = max(tmax, aw[j] - (rbase - c.lane + kTick + j) * ext);
+    return tmax;
 }
 
 // CD: fast ticks run in the column-shifted domain (run_tick_cd); needs
