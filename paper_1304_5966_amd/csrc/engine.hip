@@ -45,8 +45,10 @@
 //    max(running best, target), or if it lies outside the kept diagonal band.
 //    A skipped tick outputs lower bounds (0 / -inf).  Exact by induction along
 //    an optimal path.  Tasks entirely outside the band get no ticket.
-//  * Fast ticks run in a column-shifted domain (run_tick_cd), for both
-//    recurrences, whenever the scores fit it.
+//  * Fast ticks run in a shifted domain, for both recurrences, whenever the
+//    scores fit it: every value carries (stripe row + tick column) * ext for
+//    R = 4 and 8 rows per lane (run_tick_rs), (tick column) * ext for R = 6
+//    (run_tick_cd).
 //  * First cell of the best score: a tick whose cells can reach max(running
 //    best, target) (by the border bound above, over the tick's 127 columns)
 //    keeps its lanes' maximum; if a lane reaches it, the tick is replayed from
@@ -244,7 +246,7 @@ struct RowBest {
 
 struct TickCtx {
     const int2* in;       // LDS: 64 lane-0 inputs {H, F-candidate} of this tick
-    const int2* in_cd;    // the same inputs plus m * ext (column-shifted domain, step m)
+    const int2* in_cd;    // the same inputs plus m * ext at step m (H one ext less under the row shift)
     int2* out;            // LDS: 64 lane-63 outputs
     const uint32_t* bring;  // LDS: the tick's column codes, dwords from bbase on (shifted ticks)
     const uint32_t* prof;   // LDS: this lane's query-profile entry of class 0 (matrix scoring)
@@ -649,8 +651,9 @@ __device__ __forceinline__ int run_tick_rs(WaveState<R>& s, const uint8_t* first
     return tmax;
 }
 
-// CD: fast ticks run in the column-shifted domain (run_tick_cd); needs
-// match + ext <= 127 so that s + ext fits the score bytes.
+// CD: fast ticks run in a shifted domain (run_tick_rs for R = 4 and 8,
+// run_tick_cd for R = 6); needs match + 2 ext (R = 4, 8) or match + ext (R = 6)
+// <= 127 so that the shifted scores fit the score bytes.
 // OCC: resident waves per SIMD the register allocation is sized for
 // (512 / OCC VGPRs per lane).
 // PROT: matrix scoring; the query profile takes p.sub.n_class * 64 * (4 or 8)
@@ -1332,7 +1335,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 }
 
 // The banded global passes (reverse pass, reconstruction halves) with K waves per
-// workgroup linked through LDS; DNA scores in the column-shifted domain.
+// workgroup linked through LDS; DNA scores in the shifted domain.
 template <int R, int K, int OCC>
 __global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(OCC))) void chain_kernel(EngineArgs p) {
     engine_body<R, false, true, OCC, false, K>(p);

@@ -196,8 +196,8 @@ hipError_t launch_encode(const uint8_t* src, int64_t n, uint8_t* dst, int64_t pa
 hipError_t launch_encode_many(const uint8_t* src, const int64_t* src_off, const int64_t* dst_off,
                               const int64_t* len, int64_t n, uint8_t* dst, const EncTable& tab,
                               unsigned long long* bad, hipStream_t st);
-// cd: run the fast ticks in the column-shifted domain (requires every
-// substitution score plus gap_extend within -127..127).
+// cd: run the fast ticks in the shifted domain (requires every substitution
+// score plus cd_bias_ext(rows_per_lane) * gap_extend within -127..127).
 // waves_per_cu picks the register budget: rows_per_lane 8 and 6 run 2 waves per
 // SIMD (256 VGPRs) up to 8 waves per CU and 3 (168 VGPRs) above; rows_per_lane 4 runs 4.
 // Matrix scoring (args.sub.n_class > 0) runs the same shapes; its launches take
