@@ -147,16 +147,20 @@ def test_workspace_limit(orc):
 
 
 def test_other_scorings(ctx, orc):
-    """Includes scorings at and beyond match + gap_extend = 127, where the local pass leaves the
-    column-shifted domain for the plain one."""
+    """Includes scorings at and beyond the limits of the shifted ticks: match + 2 gap_extend = 127
+    for 4 and 8 rows per lane (their score bytes hold s + 2 ext), match + gap_extend = 127 for 6;
+    beyond them the pass runs the plain domain."""
     rng = np.random.default_rng(11)
     for sc in [(2, 1, 3, 1), (1, 1, 2, 2), (3, 2, 7, 1), (5, 4, 12, 3), (100, 120, 30, 27), (100, 3, 30, 28),
-               (1, 3, 150, 130), (1, 127, 2, 1)]:
+               (1, 3, 150, 130), (1, 127, 2, 1), (61, 3, 40, 33), (63, 2, 40, 33)]:
         p = synth.homologous_pair(int(rng.integers(1 << 30)), 1200, 1100, 0.2)
         a, b = p.a.tobytes(), p.b.tobytes()
         _case(f"scoring {sc}")
-        assert ctx.score(a, b, scoring=sc).key() == orc.sw_score(a, b, sc)
-        assert ctx.score(a, b, scoring=sc, prune=1, rows_per_lane=4).key() == orc.sw_score(a, b, sc)
+        exp = orc.sw_score(a, b, sc)
+        assert ctx.score(a, b, scoring=sc).key() == exp
+        assert ctx.score(a, b, scoring=sc, prune=1, rows_per_lane=4).key() == exp
+        assert ctx.score(a, b, scoring=sc, rows_per_lane=6).key() == exp
+        assert ctx.score(a, b, scoring=sc, rows_per_lane=8).key() == exp
 
 
 def test_external_threshold_is_exact_when_reached(ctx, orc):
